@@ -1,0 +1,291 @@
+"""Seeded synthetic mesh pairs for the two-mesh collision pipeline.
+
+This module only builds inputs: vertex positions, triangle index arrays and
+the run parameters of each workload.  It holds none of the method's
+arithmetic (no orientation predicates, no constraints, no solves), so both
+the CPU oracle and the HIP path can consume its output without sharing any
+of the computation under test.
+
+Conventions shared by every generator:
+  * positions are float64 arrays of shape [nv, 3] (cast by the caller or by
+    ``Pair.cast`` to the workload's storage type);
+  * triangles are int32 arrays of shape [nt, 3]; on an oriented (closed)
+    surface the vertex order is counter-clockwise seen from outside, so the
+    right-hand normal (b - a) x (c - a) points to the front (outside);
+  * ``orientation`` is one of ORIENT_B (only mesh B is oriented), ORIENT_A
+    (only mesh A) or ORIENT_BOTH.
+
+The paper's own models (the spike and sheet, the 576-vertex tori, the dummy
+and its garment) are not available; the workloads below stand in for them
+with the shapes of the paper's experiments (Section 6).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+ORIENT_B = 0
+ORIENT_A = 1
+ORIENT_BOTH = 2
+
+F32 = "f32"
+F64 = "f64"
+
+
+@dataclasses.dataclass
+class Pair:
+    """One resolve request: edge-side mesh A, face-side mesh B and parameters."""
+
+    name: str
+    pos_a: np.ndarray
+    tri_a: np.ndarray
+    pos_b: np.ndarray
+    tri_b: np.ndarray
+    orientation: int = ORIENT_B
+    d: float = 1e-3
+    dtype: str = F64
+    tier: int = 1  # 0: FP32 filter first, 1: FP64 filter first
+
+    def cast(self) -> "Pair":
+        """Round positions to the storage type (RNE) and return self."""
+        if self.dtype == F32:
+            self.pos_a = np.ascontiguousarray(self.pos_a, dtype=np.float32)
+            self.pos_b = np.ascontiguousarray(self.pos_b, dtype=np.float32)
+        else:
+            self.pos_a = np.ascontiguousarray(self.pos_a, dtype=np.float64)
+            self.pos_b = np.ascontiguousarray(self.pos_b, dtype=np.float64)
+        self.tri_a = np.ascontiguousarray(self.tri_a, dtype=np.int32)
+        self.tri_b = np.ascontiguousarray(self.tri_b, dtype=np.int32)
+        return self
+
+    @property
+    def sizes(self) -> dict:
+        return {
+            "nv_a": int(len(self.pos_a)), "nt_a": int(len(self.tri_a)),
+            "nv_b": int(len(self.pos_b)), "nt_b": int(len(self.tri_b)),
+        }
+
+
+# --------------------------------------------------------------------------
+# primitive surfaces
+# --------------------------------------------------------------------------
+
+def signed_volume(pos: np.ndarray, tri: np.ndarray) -> float:
+    """Signed enclosed volume; positive for a closed, outward-wound mesh."""
+    p = np.asarray(pos, dtype=np.float64)
+    a, b, c = p[tri[:, 0]], p[tri[:, 1]], p[tri[:, 2]]
+    return float(np.einsum("ij,ij->i", a, np.cross(b, c)).sum() / 6.0)
+
+
+def _orient_outward(pos: np.ndarray, tri: np.ndarray) -> np.ndarray:
+    if signed_volume(pos, tri) < 0:
+        tri = tri[:, [0, 2, 1]]
+    return np.ascontiguousarray(tri, dtype=np.int32)
+
+
+def icosphere(subdiv: int, radius: float = 1.0):
+    """Subdivided icosahedron: 10*4^s+2 vertices, 20*4^s triangles, outward CCW."""
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    v = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            v.append((0.0, s1, s2 * phi))
+            v.append((s1, s2 * phi, 0.0))
+            v.append((s2 * phi, 0.0, s1))
+    verts = [np.array(x) / np.linalg.norm(x) for x in v]
+    # faces of the icosahedron: triples of mutually adjacent vertices
+    # (adjacent = at the minimum pairwise distance)
+    P = np.array(verts)
+    dist = np.linalg.norm(P[:, None, :] - P[None, :, :], axis=2)
+    edge_len = np.min(dist[dist > 1e-9])
+    adj = np.abs(dist - edge_len) < 1e-6
+    faces = []
+    for i in range(12):
+        for j in range(i + 1, 12):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, 12):
+                if adj[i, k] and adj[j, k]:
+                    a, b, c = P[i], P[j], P[k]
+                    if np.dot(np.cross(b - a, c - a), a + b + c) < 0:
+                        faces.append((i, k, j))
+                    else:
+                        faces.append((i, j, k))
+    assert len(faces) == 20
+    for _ in range(subdiv):
+        cache = {}
+        new_faces = []
+
+        def mid(i, j):
+            key = (min(i, j), max(i, j))
+            if key not in cache:
+                m = verts[i] + verts[j]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        for (a, b, c) in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            new_faces += [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
+        faces = new_faces
+    pos = np.array(verts) * radius
+    tri = np.array(faces, dtype=np.int32)
+    return pos, _orient_outward(pos, tri)
+
+
+def uv_sphere(n_rings: int, n_seg: int, radius: float = 1.0):
+    """Latitude/longitude sphere with poles; 2*n_seg*(n_rings-1) triangles."""
+    verts = [(0.0, 0.0, radius)]
+    for i in range(1, n_rings):
+        th = math.pi * i / n_rings
+        for j in range(n_seg):
+            ph = 2.0 * math.pi * j / n_seg
+            verts.append((radius * math.sin(th) * math.cos(ph),
+                          radius * math.sin(th) * math.sin(ph),
+                          radius * math.cos(th)))
+    verts.append((0.0, 0.0, -radius))
+    south = len(verts) - 1
+
+    def ring(i, j):
+        return 1 + (i - 1) * n_seg + (j % n_seg)
+
+    faces = []
+    for j in range(n_seg):
+        faces.append((0, ring(1, j), ring(1, j + 1)))
+    for i in range(1, n_rings - 1):
+        for j in range(n_seg):
+            a, b = ring(i, j), ring(i, j + 1)
+            c, d = ring(i + 1, j), ring(i + 1, j + 1)
+            faces += [(a, c, d), (a, d, b)]
+    for j in range(n_seg):
+        faces.append((south, ring(n_rings - 1, j + 1), ring(n_rings - 1, j)))
+    pos = np.array(verts, dtype=np.float64)
+    return pos, _orient_outward(pos, np.array(faces, dtype=np.int32))
+
+
+def grid_sheet(nx: int, ny: int, side: float, z: float = 0.0):
+    """Flat nx-by-ny vertex grid on [-side/2, side/2]^2 at height z.
+
+    Each cell (i, j) is split along its (i, j)-(i+1, j+1) diagonal, giving
+    2*(nx-1)*(ny-1) triangles, wound counter-clockwise seen from +z.
+    """
+    xs = np.linspace(-side / 2, side / 2, nx)
+    ys = np.linspace(-side / 2, side / 2, ny)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), np.full(nx * ny, z)], axis=1)
+
+    def vid(i, j):
+        return i * ny + j
+
+    faces = []
+    for i in range(nx - 1):
+        for j in range(ny - 1):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            faces += [(a, b, c), (a, c, d)]
+    return pos, np.array(faces, dtype=np.int32)
+
+
+def torus(nu: int, nv: int, R: float = 1.0, r: float = 0.3):
+    """Torus about the z axis: nu major x nv minor segments, outward CCW."""
+    i = np.arange(nu)[:, None]
+    j = np.arange(nv)[None, :]
+    th = 2.0 * np.pi * i / nu
+    ph = 2.0 * np.pi * j / nv
+    x = (R + r * np.cos(ph)) * np.cos(th)
+    y = (R + r * np.cos(ph)) * np.sin(th)
+    z = r * np.sin(ph) * np.ones_like(th)
+    pos = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    faces = []
+    for a_i in range(nu):
+        for a_j in range(nv):
+            a = a_i * nv + a_j
+            b = ((a_i + 1) % nu) * nv + a_j
+            c = ((a_i + 1) % nu) * nv + (a_j + 1) % nv
+            d = a_i * nv + (a_j + 1) % nv
+            faces += [(a, b, c), (a, c, d)]
+    return pos, _orient_outward(pos, np.array(faces, dtype=np.int32))
+
+
+def rot_x(deg: float) -> np.ndarray:
+    t = math.radians(deg)
+    c, s = math.cos(t), math.sin(t)
+    return np.array([[1.0, 0.0, 0.0], [0.0, c, -s], [0.0, s, c]])
+
+
+def random_rotation(rng: np.random.Generator) -> np.ndarray:
+    """Uniform random proper rotation (QR of a Gaussian matrix)."""
+    q, rr = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q @ np.diag(np.sign(np.diag(rr)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def edges_of(tri: np.ndarray) -> np.ndarray:
+    """Unique undirected edges (u < v), lexicographically sorted (for sizes)."""
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    e = np.sort(e, axis=1)
+    return np.unique(e, axis=0)
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def sphere_sheet(seed: int = 1, subdiv: int = 3, grid: int = 32, side: float = 2.5,
+                 z: float = 0.3, sigma: float = 0.01, dtype: str = F64, tier: int = 1) -> Pair:
+    """Oriented icosphere (mesh B, radius 1) pierced by a flat cloth sheet (mesh A).
+
+    Default sizes: icosphere subdivision 3 (642 vertices, 1280 triangles) and a
+    32x32 sheet of side 2.5 (1024 vertices, 1922 triangles) at z = 0.3, with
+    N(0, sigma^2) jitter on every coordinate of both meshes.
+    """
+    rng = np.random.default_rng(seed)
+    pb, tb = icosphere(subdiv, 1.0)
+    pa, ta = grid_sheet(grid, grid, side, z)
+    pa = pa + rng.normal(0.0, sigma, pa.shape)
+    pb = pb + rng.normal(0.0, sigma, pb.shape)
+    return Pair("sphere_sheet", pa, ta, pb, tb, ORIENT_B, 1e-3, dtype, tier).cast()
+
+
+def linked_tori(nu: int = 128, nv: int = 64, R: float = 1.0, r: float = 0.3,
+                shift: float = 1.7, dtype: str = F32, tier: int = 0) -> Pair:
+    """Two oriented tori; the second is rotated 90 degrees about x, then shifted along x.
+
+    With the defaults each torus has 8192 vertices and 16384 triangles and the
+    tubes overlap to a depth of 0.3 near x = 0.7 .. 1.0.
+    """
+    pa, ta = torus(nu, nv, R, r)
+    pb, tb = torus(nu, nv, R, r)
+    pb = pb @ rot_x(90.0).T + np.array([shift, 0.0, 0.0])
+    return Pair("linked_tori", pa, ta, pb, tb, ORIENT_BOTH, 1e-3, dtype, tier).cast()
+
+
+def random_small_pair(seed: int, kind: str = "sphere_sheet") -> Pair:
+    """Tiny randomly placed pairs (tens to a few hundred triangles) for brute-force checks."""
+    rng = np.random.default_rng(seed)
+    if kind == "sphere_sheet":
+        pb, tb = icosphere(int(rng.integers(0, 2)), 1.0)
+        n = int(rng.integers(4, 9))
+        pa, ta = grid_sheet(n, n, 2.5, float(rng.uniform(-0.8, 0.8)))
+        pa = pa @ random_rotation(rng).T
+        pa = pa + rng.normal(0.0, 0.02, pa.shape)
+        pb = pb + rng.normal(0.0, 0.02, pb.shape)
+        return Pair(f"small_ss_{seed}", pa, ta, pb, tb, ORIENT_B, 1e-3, F64, 1).cast()
+    nu = int(rng.integers(6, 12))
+    pa, ta = torus(nu, max(3, nu // 2), 1.0, 0.3)
+    pb, tb = torus(nu, max(3, nu // 2), 1.0, 0.3)
+    pb = pb @ rot_x(90.0).T + np.array([float(rng.uniform(1.45, 1.75)), 0.0, 0.0])
+    pa = pa + rng.normal(0.0, 0.01, pa.shape)
+    pb = pb + rng.normal(0.0, 0.01, pb.shape)
+    return Pair(f"small_tt_{seed}", pa, ta, pb, tb, ORIENT_BOTH, 1e-3, F32, 0).cast()
+
+
+def workload(name: str, **kw) -> Pair:
+    if name == "sphere_sheet":
+        return sphere_sheet(**kw)
+    if name == "linked_tori":
+        return linked_tori(**kw)
+    raise KeyError(name)
