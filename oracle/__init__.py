@@ -300,10 +300,16 @@ def solve_min_norm(A, r, rcut: float = 1e-12):
     return lam, int(np.count_nonzero(~keep))
 
 
-def respond(xa, xb, ta, tb, st, d, wa=None, wb=None):
+class ZoneLimit(Exception):
+    """An impact zone larger than the caller's limit (no position was changed)."""
+
+
+def respond(xa, xb, ta, tb, st, d, wa=None, wb=None, max_zone=None):
     """One response: relocate the stencil vertices (Eq. 3 - Eq. 8), per impact zone.
 
     Returns (new xa, new xb, info) with positions in float64 (no storage rounding).
+    Raises ZoneLimit, before moving anything, if a zone has more than
+    ``max_zone`` stencils.
     """
     xa = np.array(xa, dtype=np.float64)
     xb = np.array(xb, dtype=np.float64)
@@ -314,6 +320,8 @@ def respond(xa, xb, ta, tb, st, d, wa=None, wb=None):
     X = np.concatenate([xa, xb])
     Xn = X.copy()
     zones = impact_zones(con["verts"])
+    if max_zone is not None and max(len(z) for z in zones) > max_zone:
+        raise ZoneLimit(max(len(z) for z in zones))
     lam_all = np.full(len(st), np.nan)
     n_cut = 0
     for idx in zones:
@@ -342,8 +350,15 @@ def respond(xa, xb, ta, tb, st, d, wa=None, wb=None):
 
 def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 1e-3,
             dtype: str = "f64", max_rounds: int = 256, mode: int = MODE_ALTERNATE,
-            inv_mass_a=None, inv_mass_b=None, nthreads: int = 1, record: bool = False):
+            inv_mass_a=None, inv_mass_b=None, nthreads: int = 1, record: bool = False,
+            round_offset: int = 0, max_zone: int | None = None):
     """The repair loop of Section 3: detect, relocate, repeat until no E-F hit.
+
+    ``round_offset`` shifts the round numbering that decides, when both meshes
+    are oriented, which one plays the oriented role first (round r uses mesh
+    B's faces when r + round_offset is even).  With ``max_zone``, a round whose
+    largest impact zone exceeds it ends the loop (status "zone_limit") with
+    the positions from before that round.
 
     At most ``max_rounds`` responses are made; the loop then reports
     ``converged = False`` with the residual hit count.  Returns a dict with
@@ -360,6 +375,7 @@ def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 
     rounds = []
     hits0 = np.zeros((0, 5), np.int32)
     converged = False
+    status = "not_converged"
     r = 0
 
     def det(direction):
@@ -370,7 +386,7 @@ def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 
 
     for r in range(max_rounds + 1):
         if orientation == ORIENT_BOTH and mode == MODE_ALTERNATE:
-            first = r % 2
+            first = (r + round_offset) % 2
             h1 = det(first)
             h2 = det(1 - first) if (r == 0 or len(h1) == 0) else np.zeros((0, 5), np.int32)
             if r == 0:
@@ -387,7 +403,11 @@ def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 
         if r == max_rounds:
             break
         st = stencils(active)
-        xa_new, xb_new, info = respond(xa, xb, ta, tb, st, d, inv_mass_a, inv_mass_b)
+        try:
+            xa_new, xb_new, info = respond(xa, xb, ta, tb, st, d, inv_mass_a, inv_mass_b, max_zone)
+        except ZoneLimit:
+            status = "zone_limit"
+            break
         if dtype == "f32":
             xa_new = xa_new.astype(np.float32).astype(np.float64)
             xb_new = xb_new.astype(np.float32).astype(np.float64)
@@ -402,13 +422,15 @@ def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 
         rounds.append(rec)
         xa, xb = xa_new, xb_new
     residual = 0
-    if not converged:
+    if converged:
+        status = "ok"
+    elif status != "zone_limit":
         residual = sum(len(det(dr)) for dr in oriented)
     out_t = np.float32 if dtype == "f32" else np.float64
     return {
         "pos_a": xa.astype(out_t), "pos_b": xb.astype(out_t),
         "hits0": hits0, "stencils0": stencils(hits0),
-        "rounds": len(rounds), "converged": converged, "residual": residual,
+        "rounds": len(rounds), "converged": converged, "residual": residual, "status": status,
         "per_round": rounds, "candidates": cand_total,
     }
 

@@ -1,0 +1,260 @@
+"""Python binding of libhfcr.so: history-free collision response on gfx950.
+
+Argument marshalling only: every step of detection and response runs in the
+library's HIP kernels.  PyTorch supplies device memory and the stream.  The
+library must be built (``python -m paper_1409_2081_amd.build`` or
+``__graft_entry__.build()``); there is no fallback path, so a missing library
+or device raises.
+
+Entry points mirror include/hfcr.h: ``Context.resolve``, ``Context.detect``
+and ``Context.test_orient``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhfcr.so")
+
+HFCR_OK = 0
+HFCR_NOT_CONVERGED = 1
+HFCR_E_INVALID = -1
+HFCR_E_CAPACITY = -2
+HFCR_E_OOM = -3
+HFCR_E_DEVICE = -4
+HFCR_E_ZONE_LIMIT = -5
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_OOM",
+                -4: "E_DEVICE", -5: "E_ZONE_LIMIT"}
+
+HFCR_F32 = 0
+HFCR_F64 = 1
+ORIENT_B = 0
+ORIENT_A = 1
+ORIENT_BOTH = 2
+BOTH_ALTERNATE = 0
+BOTH_SIMULTANEOUS = 1
+FLAG_TIMING = 1
+MAX_ZONE = 4096
+STAT_ROUNDS = 64
+STAGES = 8
+STAGE_NAMES = ["setup", "refit", "traverse", "exact", "stencils", "zones", "solve", "update"]
+
+EXPORTED = ["hfcr_default_opts", "hfcr_create", "hfcr_destroy", "hfcr_last_error", "hfcr_detect",
+            "hfcr_resolve", "hfcr_test_orient"]
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("nv", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("pos", ctypes.c_void_p), ("tri", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_rounds", ctypes.c_int32), ("both_mode", ctypes.c_int32),
+                ("predicate_tier", ctypes.c_int32), ("round_offset", ctypes.c_int32),
+                ("inv_mass_a", ctypes.c_void_p), ("inv_mass_b", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("residual_hits", ctypes.c_int64), ("hits0", ctypes.c_int64),
+                ("stencils0", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("exact_tests", ctypes.c_int64), ("f32_ambiguous", ctypes.c_int64),
+                ("max_zone", ctypes.c_int32), ("rank_deficient", ctypes.c_int32),
+                ("stage_ms", ctypes.c_double * STAGES), ("stage_calls", ctypes.c_int32 * STAGES),
+                ("round_hits", ctypes.c_int32 * STAT_ROUNDS),
+                ("round_stencils", ctypes.c_int32 * STAT_ROUNDS),
+                ("round_zones", ctypes.c_int32 * STAT_ROUNDS),
+                ("round_max_zone", ctypes.c_int32 * STAT_ROUNDS)]
+
+    def to_dict(self) -> dict:
+        n = min(self.rounds + 1, STAT_ROUNDS)
+        return {
+            "rounds": self.rounds, "converged": bool(self.converged),
+            "residual_hits": self.residual_hits, "hits0": self.hits0, "stencils0": self.stencils0,
+            "candidates": self.candidates, "exact_tests": self.exact_tests,
+            "f32_ambiguous": self.f32_ambiguous, "max_zone": self.max_zone,
+            "rank_deficient": self.rank_deficient,
+            "stage_ms": {STAGE_NAMES[i]: self.stage_ms[i] for i in range(STAGES)},
+            "stage_calls": {STAGE_NAMES[i]: self.stage_calls[i] for i in range(STAGES)},
+            "round_hits": list(self.round_hits[:n]), "round_stencils": list(self.round_stencils[:n]),
+            "round_zones": list(self.round_zones[:n]), "round_max_zone": list(self.round_max_zone[:n]),
+        }
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("pos_a_out", ctypes.c_void_p), ("pos_b_out", ctypes.c_void_p),
+                ("hits", ctypes.c_void_p), ("hit_cap", ctypes.c_int64),
+                ("stencils", ctypes.c_void_p), ("stencil_cap", ctypes.c_int64),
+                ("stats", ctypes.POINTER(Stats))]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libhfcr.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1409_2081_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.hfcr_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.hfcr_default_opts.restype = None
+        L.hfcr_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.hfcr_create.restype = ctypes.c_int
+        L.hfcr_destroy.argtypes = [vp]
+        L.hfcr_destroy.restype = None
+        L.hfcr_last_error.argtypes = [vp]
+        L.hfcr_last_error.restype = ctypes.c_char_p
+        L.hfcr_detect.argtypes = [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Mesh), ctypes.c_int32,
+                                  ctypes.POINTER(Opts), ctypes.POINTER(Result), vp]
+        L.hfcr_detect.restype = ctypes.c_int
+        L.hfcr_resolve.argtypes = [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Mesh), ctypes.c_int32,
+                                   ctypes.c_double, ctypes.POINTER(Opts), ctypes.POINTER(Result), vp]
+        L.hfcr_resolve.restype = ctypes.c_int
+        L.hfcr_test_orient.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
+        L.hfcr_test_orient.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+class HfcrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _mesh(pos, tri) -> Mesh:
+    torch = _torch()
+    if not (pos.is_cuda and tri.is_cuda):
+        raise ValueError("positions and triangles must be device tensors")
+    if pos.dtype not in (torch.float32, torch.float64) or tri.dtype != torch.int32:
+        raise ValueError("positions must be float32/float64 and triangles int32")
+    if pos.dim() != 2 or pos.shape[1] != 3 or tri.dim() != 2 or tri.shape[1] != 3:
+        raise ValueError("positions must be [nv,3] and triangles [nt,3]")
+    if not (pos.is_contiguous() and tri.is_contiguous()):
+        raise ValueError("arrays must be contiguous")
+    return Mesh(HFCR_F32 if pos.dtype == torch.float32 else HFCR_F64, pos.shape[0], tri.shape[0], 0,
+                pos.data_ptr() if pos.numel() else None, tri.data_ptr() if tri.numel() else None)
+
+
+class Context:
+    """One library context on a GPU (owns the device workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        st = self._L.hfcr_create(ctypes.byref(h), int(device))
+        if st != HFCR_OK:
+            raise HfcrError(st, "hfcr_create failed")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.hfcr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self._L.hfcr_last_error(self._h).decode()
+
+    @staticmethod
+    def _opts(max_rounds=256, both_mode=BOTH_ALTERNATE, tier=0, round_offset=0, inv_mass_a=None,
+              inv_mass_b=None, timing=False) -> Opts:
+        o = Opts()
+        lib().hfcr_default_opts(ctypes.byref(o))
+        o.max_rounds = int(max_rounds)
+        o.both_mode = int(both_mode)
+        o.predicate_tier = int(tier)
+        o.round_offset = int(round_offset)
+        o.inv_mass_a = inv_mass_a.data_ptr() if inv_mass_a is not None else None
+        o.inv_mass_b = inv_mass_b.data_ptr() if inv_mass_b is not None else None
+        o.flags = FLAG_TIMING if timing else 0
+        return o
+
+    def resolve(self, pos_a, tri_a, pos_b, tri_b, orientation=ORIENT_B, d=1e-3, *, hit_cap=1 << 16,
+                stencil_cap=1 << 16, want_lists=True, raise_on_error=True, stream=None, **opt_kw) -> dict:
+        """hfcr_resolve: returns positions, round-0 hits/stencils, stats and status."""
+        torch = _torch()
+        ma, mb = _mesh(pos_a, tri_a), _mesh(pos_b, tri_b)
+        out_a, out_b = torch.empty_like(pos_a), torch.empty_like(pos_b)
+        hits = torch.empty((hit_cap, 5), dtype=torch.int32, device=pos_a.device) if want_lists else None
+        sten = torch.empty((stencil_cap, 3), dtype=torch.int32, device=pos_a.device) if want_lists else None
+        stats = Stats()
+        res = Result(out_a.data_ptr() if out_a.numel() else None,
+                     out_b.data_ptr() if out_b.numel() else None,
+                     hits.data_ptr() if hits is not None else None, hit_cap,
+                     sten.data_ptr() if sten is not None else None, stencil_cap,
+                     ctypes.pointer(stats))
+        o = self._opts(**opt_kw)
+        s = stream if stream is not None else torch.cuda.current_stream(pos_a.device).cuda_stream
+        st = self._L.hfcr_resolve(self._h, ctypes.byref(ma), ctypes.byref(mb), int(orientation), float(d),
+                                  ctypes.byref(o), ctypes.byref(res), ctypes.c_void_p(s))
+        if st == HFCR_E_CAPACITY and want_lists:
+            return self.resolve(pos_a, tri_a, pos_b, tri_b, orientation, d,
+                                hit_cap=max(hit_cap, stats.hits0), stencil_cap=max(stencil_cap, stats.stencils0),
+                                want_lists=True, raise_on_error=raise_on_error, stream=stream, **opt_kw)
+        if st < 0 and st != HFCR_E_ZONE_LIMIT and raise_on_error:
+            raise HfcrError(st, self.last_error())
+        out = {"status": st, "status_name": STATUS_NAMES.get(st, str(st)), "pos_a": out_a, "pos_b": out_b,
+               "stats": stats.to_dict()}
+        if st == HFCR_E_ZONE_LIMIT:
+            out["error"] = self.last_error()
+        if want_lists:
+            out["hits"] = hits[: min(stats.hits0, hit_cap)]
+            out["stencils"] = sten[: min(stats.stencils0, stencil_cap)]
+        return out
+
+    def detect(self, pos_a, tri_a, pos_b, tri_b, orientation=ORIENT_B, *, hit_cap=1 << 16,
+               stencil_cap=1 << 16, stream=None, **opt_kw) -> dict:
+        """hfcr_detect: one DCD pass; returns hits, stencils and stats."""
+        torch = _torch()
+        ma, mb = _mesh(pos_a, tri_a), _mesh(pos_b, tri_b)
+        hits = torch.empty((hit_cap, 5), dtype=torch.int32, device=pos_a.device)
+        sten = torch.empty((stencil_cap, 3), dtype=torch.int32, device=pos_a.device)
+        stats = Stats()
+        res = Result(None, None, hits.data_ptr(), hit_cap, sten.data_ptr(), stencil_cap, ctypes.pointer(stats))
+        o = self._opts(**opt_kw)
+        s = stream if stream is not None else torch.cuda.current_stream(pos_a.device).cuda_stream
+        st = self._L.hfcr_detect(self._h, ctypes.byref(ma), ctypes.byref(mb), int(orientation),
+                                 ctypes.byref(o), ctypes.byref(res), ctypes.c_void_p(s))
+        if st == HFCR_E_CAPACITY:
+            return self.detect(pos_a, tri_a, pos_b, tri_b, orientation, hit_cap=max(hit_cap, stats.hits0),
+                               stencil_cap=max(stencil_cap, stats.stencils0), stream=stream, **opt_kw)
+        if st < 0:
+            raise HfcrError(st, self.last_error())
+        return {"status": st, "hits": hits[: stats.hits0], "stencils": sten[: stats.stencils0],
+                "stats": stats.to_dict()}
+
+    def test_orient(self, pts, tier: int, stream=None):
+        """Signs of orient for pts [n,4,3] float64 (device); 2 means unsure (tiers 0 and 1)."""
+        torch = _torch()
+        pts = pts.contiguous()
+        out = torch.empty(pts.shape[0], dtype=torch.int32, device=pts.device)
+        s = stream if stream is not None else torch.cuda.current_stream(pts.device).cuda_stream
+        st = self._L.hfcr_test_orient(self._h, ctypes.c_void_p(pts.data_ptr()), pts.shape[0], int(tier),
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s))
+        if st != HFCR_OK:
+            raise HfcrError(st, self.last_error())
+        return out
+
+
+def pair_tensors(pair, device="cuda"):
+    """Device tensors (pos_a, tri_a, pos_b, tri_b) of a meshgen.Pair."""
+    torch = _torch()
+    return (torch.from_numpy(pair.pos_a).to(device), torch.from_numpy(pair.tri_a).to(device),
+            torch.from_numpy(pair.pos_b).to(device), torch.from_numpy(pair.tri_b).to(device))

@@ -1,0 +1,770 @@
+// C ABI and host runtime: workspace management, per-call set-up (ingest,
+// edges, Morton orders, BVH build), the detect / respond repair loop and
+// status reporting.  Every arithmetic step runs in the kernels; the host
+// only sequences launches and reads back the counts that size the next step.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hfcr.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace hfcr;
+
+namespace {
+
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Counters {
+  uint32_t err;
+  uint32_t maxabs[2];
+  uint32_t hit_count[2];
+  uint32_t amb_count[2];
+  int32_t overflow;
+  uint32_t total;
+  uint32_t nzones;
+  uint32_t maxk;
+  int32_t rank_def;
+  uint32_t pad[3];
+  unsigned long long cand;
+  unsigned long long f32_unsure;
+  unsigned long long exact;
+};
+
+struct Timer {
+  int stage;
+  hipEvent_t a, b;
+};
+
+int bits_for(int64_t n) {  // bits to hold values 0..n-1 (at least 1)
+  int b = 1;
+  while (b < 62 && (1ll << b) < n) ++b;
+  return b;
+}
+
+struct HipError {
+  hipError_t e;
+  const char *what;
+};
+
+}  // namespace
+
+struct hfcr_ctx {
+  int device = 0;
+  std::string err;
+  hipStream_t s = nullptr;
+  // per mesh
+  DBuf x64[2], x32[2], edges[2], qedges[2], leaf_tri[2], nodes[2], leaf_parent[2], counters_n[2], root_box[2],
+      codes[2], scene_box[2];
+  // detection
+  DBuf hk[2], hv[2], amb[2];
+  // generic sort / scan scratch
+  DBuf sk0, sk1, sv0, sv1, hist, flags, pos, bsums;
+  // response
+  DBuf st_keys, st_out_keys, con, parent, zkeys, zvals, starts, lambda, inc_keys, solve_scratch;
+  DBuf ctr;
+  Counters *hctr = nullptr;  // pinned
+  std::vector<Timer> timers;
+  std::vector<hipEvent_t> free_events;
+  bool timing = false;
+};
+
+namespace {
+
+#define HIP_CHECK(x)                                   \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) throw HipError{e_, #x};      \
+  } while (0)
+
+struct StatusError {
+  hfcr_status st;
+  std::string msg;
+};
+
+void ensure(DBuf &b, size_t bytes, bool zero = false) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return;
+  const size_t old = b.bytes;
+  if (b.p) HIP_CHECK(hipFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  size_t want = std::max(bytes, old + old / 2);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw StatusError{HFCR_E_OOM, "device allocation of " + std::to_string(want) + " bytes failed"};
+  }
+  b.bytes = want;
+  if (zero) HIP_CHECK(hipMemset(b.p, 0, want));
+}
+
+template <typename T>
+T *ptr(DBuf &b) {
+  return reinterpret_cast<T *>(b.p);
+}
+
+hipEvent_t take_event(hfcr_ctx *c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
+
+struct Scope {  // times the launches issued during its lifetime
+  hfcr_ctx *c;
+  int stage;
+  hipEvent_t a = nullptr;
+  Scope(hfcr_ctx *ctx, int st) : c(ctx), stage(st) {
+    if (c->timing) {
+      a = take_event(c);
+      HIP_CHECK(hipEventRecord(a, c->s));
+    }
+  }
+  ~Scope() {
+    // never throws: a failed record only loses this interval
+    if (c->timing && a) {
+      hipEvent_t b = nullptr;
+      if (!c->free_events.empty()) {
+        b = c->free_events.back();
+        c->free_events.pop_back();
+      } else if (hipEventCreate(&b) != hipSuccess) {
+        c->free_events.push_back(a);
+        return;
+      }
+      if (hipEventRecord(b, c->s) == hipSuccess) {
+        c->timers.push_back({stage, a, b});
+      } else {
+        c->free_events.push_back(a);
+        c->free_events.push_back(b);
+      }
+    }
+  }
+};
+
+void readback(hfcr_ctx *c) {
+  HIP_CHECK(hipMemcpyAsync(c->hctr, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->s));
+  HIP_CHECK(hipStreamSynchronize(c->s));
+}
+
+// Sort (k, v) of length n in place, using the context's alternate buffers.
+void sort_inplace(hfcr_ctx *c, uint64_t *k, uint32_t *v, int64_t n, int key_bits) {
+  if (n <= 1) return;
+  ensure(c->sk1, n * sizeof(uint64_t));
+  if (v) ensure(c->sv1, n * sizeof(uint32_t));
+  ensure(c->hist, radix_hist_entries(n) * sizeof(uint32_t));
+  SortBufs b{k, ptr<uint64_t>(c->sk1), v, v ? ptr<uint32_t>(c->sv1) : nullptr, ptr<uint32_t>(c->hist),
+             radix_hist_entries(n)};
+  bool alt = false;
+  sort_pairs(b, n, key_bits, c->s, alt);
+  if (alt) {
+    HIP_CHECK(hipMemcpyAsync(k, c->sk1.p, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
+    if (v) HIP_CHECK(hipMemcpyAsync(v, c->sv1.p, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->s));
+  }
+}
+
+// Exclusive scan of flags[0..n) into c->pos; returns the total (synchronises).
+uint32_t scan_count(hfcr_ctx *c, const uint32_t *flags, int64_t n) {
+  ensure(c->pos, n * sizeof(uint32_t));
+  ensure(c->bsums, scan_block_sums_entries(n) * sizeof(uint32_t));
+  Counters *dc = ptr<Counters>(c->ctr);
+  scan_u32(flags, ptr<uint32_t>(c->pos), n, ptr<uint32_t>(c->bsums), &dc->total, c->s);
+  readback(c);
+  return c->hctr->total;
+}
+
+struct Pair {
+  MeshDev m[2];
+  int orientation;
+  int dirs[2];
+  int ndirs;
+  HitLayout hl;
+  StencilLayout sl;
+  bool tier0;
+  bool dirty[2];
+  bool has_edges[2], has_bvh[2];
+  int64_t hit_cap[2], amb_cap[2];
+  int64_t hits_n[2];
+};
+
+void check_mesh(const hfcr_mesh *m, const char *name) {
+  if (!m) throw StatusError{HFCR_E_INVALID, std::string("mesh ") + name + " is NULL"};
+  if (m->dtype != HFCR_F32 && m->dtype != HFCR_F64)
+    throw StatusError{HFCR_E_INVALID, std::string("mesh ") + name + ": bad dtype"};
+  if (m->nv < 0 || m->nt < 0) throw StatusError{HFCR_E_INVALID, std::string("mesh ") + name + ": negative count"};
+  if (m->nt >= (1 << 24)) throw StatusError{HFCR_E_INVALID, std::string("mesh ") + name + ": more than 2^24-1 triangles"};
+  if (m->nv >= (1 << 28)) throw StatusError{HFCR_E_INVALID, std::string("mesh ") + name + ": more than 2^28-1 vertices"};
+  if ((m->nv > 0 && !m->pos) || (m->nt > 0 && !m->tri))
+    throw StatusError{HFCR_E_INVALID, std::string("mesh ") + name + ": NULL array"};
+}
+
+void setup_mesh(hfcr_ctx *c, Pair &P, int i, const hfcr_mesh *src, const double *inv_mass) {
+  MeshDev &m = P.m[i];
+  m.nv = src->nv;
+  m.nt = src->nt;
+  m.ne = 0;
+  m.f32 = src->dtype == HFCR_F32;
+  m.pos_in = src->pos;
+  m.tri_in = src->tri;
+  m.inv_mass = inv_mass;
+  ensure(c->x64[i], (size_t)3 * m.nv * sizeof(double));
+  m.x64 = ptr<double>(c->x64[i]);
+  if (m.f32) {
+    ensure(c->x32[i], (size_t)3 * m.nv * sizeof(float));
+    m.x32 = ptr<float>(c->x32[i]);
+  } else {
+    m.x32 = nullptr;
+  }
+  Counters *dc = ptr<Counters>(c->ctr);
+  launch_ingest(m, &dc->err, &dc->maxabs[i], c->s);
+}
+
+void build_edges(hfcr_ctx *c, Pair &P, int i) {
+  MeshDev &m = P.m[i];
+  const int64_t n = 3 * (int64_t)m.nt;
+  if (n == 0) {
+    m.ne = 0;
+    return;
+  }
+  ensure(c->sk0, n * sizeof(uint64_t));
+  ensure(c->flags, n * sizeof(uint32_t));
+  uint64_t *keys = ptr<uint64_t>(c->sk0);
+  launch_edge_keys(m, keys, c->s);
+  sort_inplace(c, keys, nullptr, n, 32 + bits_for((int64_t)m.nv + 1));
+  launch_unique_flags(keys, n, (uint64_t)m.nv << 32, ptr<uint32_t>(c->flags), c->s);
+  const uint32_t ne = scan_count(c, ptr<uint32_t>(c->flags), n);
+  m.ne = (int)ne;
+  ensure(c->edges[i], std::max<int64_t>(ne, 1) * sizeof(int2));
+  ensure(c->qedges[i], std::max<int64_t>(ne, 1) * sizeof(int4));
+  m.edges = ptr<int2>(c->edges[i]);
+  m.qedges = ptr<int4>(c->qedges[i]);
+  launch_compact_edges(keys, ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), n, m.edges, c->s);
+  if (ne == 0) return;
+  // queries in Morton order of the edge midpoints
+  ensure(c->scene_box[i], 6 * sizeof(float));
+  launch_bounds(m, ptr<float>(c->scene_box[i]), c->s);
+  ensure(c->sk0, (size_t)ne * sizeof(uint64_t));
+  launch_edge_morton(m, ptr<float>(c->scene_box[i]), ptr<uint64_t>(c->sk0), c->s);
+  sort_inplace(c, ptr<uint64_t>(c->sk0), nullptr, ne, -62);
+  launch_make_qedges(m, ptr<uint64_t>(c->sk0), c->s);
+  P.has_edges[i] = true;
+}
+
+void build_bvh(hfcr_ctx *c, Pair &P, int i) {
+  MeshDev &m = P.m[i];
+  const int nt = m.nt;
+  ensure(c->leaf_tri[i], std::max(nt, 1) * sizeof(int4));
+  ensure(c->nodes[i], std::max(nt, 1) * sizeof(BvhNode));
+  ensure(c->leaf_parent[i], std::max(nt, 1) * sizeof(int));
+  ensure(c->counters_n[i], std::max(nt, 1) * sizeof(int), /*zero=*/true);
+  ensure(c->root_box[i], 8 * sizeof(float));
+  ensure(c->codes[i], std::max(nt, 1) * sizeof(uint32_t));
+  ensure(c->scene_box[i], 6 * sizeof(float));
+  m.leaf_tri = ptr<int4>(c->leaf_tri[i]);
+  m.nodes = ptr<BvhNode>(c->nodes[i]);
+  m.leaf_parent = ptr<int>(c->leaf_parent[i]);
+  m.counters = ptr<int>(c->counters_n[i]);
+  m.root_box = ptr<float>(c->root_box[i]);
+  if (nt == 0) return;
+  launch_bounds(m, ptr<float>(c->scene_box[i]), c->s);
+  ensure(c->sk0, (size_t)nt * sizeof(uint64_t));
+  launch_face_morton(m, ptr<float>(c->scene_box[i]), ptr<uint64_t>(c->sk0), c->s);
+  sort_inplace(c, ptr<uint64_t>(c->sk0), nullptr, nt, -62);
+  launch_leaf_tri(m, ptr<uint64_t>(c->sk0), ptr<uint32_t>(c->codes[i]), c->s);
+  launch_build_tree(m, ptr<uint32_t>(c->codes[i]), c->s);
+  P.has_bvh[i] = true;
+  P.dirty[i] = true;
+}
+
+void reset_counters(hfcr_ctx *c) { HIP_CHECK(hipMemsetAsync(c->ctr.p, 0, sizeof(Counters), c->s)); }
+
+// One detection pass in direction dir; leaves the sorted hits in hk/hv[dir].
+int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir) {
+  const int ei = dir == 0 ? 0 : 1, fi = dir == 0 ? 1 : 0;
+  MeshDev &E = P.m[ei], &F = P.m[fi];
+  if (P.dirty[fi]) {
+    Scope t(c, 1);
+    launch_refit(F, c->s);
+    P.dirty[fi] = false;
+  }
+  Counters *dc = ptr<Counters>(c->ctr);
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    ensure(c->hk[dir], P.hit_cap[dir] * sizeof(uint64_t));
+    ensure(c->hv[dir], P.hit_cap[dir] * sizeof(uint32_t));
+    ensure(c->amb[dir], P.amb_cap[dir] * sizeof(uint2));
+    HIP_CHECK(hipMemsetAsync(&dc->hit_count[dir], 0, sizeof(uint32_t), c->s));
+    HIP_CHECK(hipMemsetAsync(&dc->amb_count[dir], 0, sizeof(uint32_t), c->s));
+    DcdOut out;
+    out.keys = ptr<uint64_t>(c->hk[dir]);
+    out.vals = ptr<uint32_t>(c->hv[dir]);
+    out.count = &dc->hit_count[dir];
+    out.cap = P.hit_cap[dir];
+    out.amb = ptr<uint2>(c->amb[dir]);
+    out.amb_count = &dc->amb_count[dir];
+    out.amb_cap = P.amb_cap[dir];
+    out.cand = &dc->cand;
+    out.f32_unsure = &dc->f32_unsure;
+    out.exact = &dc->exact;
+    out.overflow = &dc->overflow;
+    {
+      Scope t(c, 2);
+      launch_traverse(E, F, dir, P.tier0, P.hl, out, c->s);
+    }
+    {
+      Scope t(c, 3);
+      launch_exact(E, F, dir, P.hl, out, c->s);
+    }
+    readback(c);
+    if (c->hctr->overflow) throw StatusError{HFCR_E_DEVICE, "BVH traversal stack overflow"};
+    const int64_t nh = c->hctr->hit_count[dir], na = c->hctr->amb_count[dir];
+    if (nh <= P.hit_cap[dir] && na <= P.amb_cap[dir]) {
+      Scope t(c, 4);
+      sort_inplace(c, out.keys, out.vals, nh, 1 + P.hl.bits_e + P.hl.bits_f);
+      P.hits_n[dir] = nh;
+      return nh;
+    }
+    // capacity exceeded: grow and redo this pass (candidates are counted twice)
+    P.hit_cap[dir] = std::max<int64_t>(P.hit_cap[dir], nh + nh / 2 + 64);
+    P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], na + na / 2 + 64);
+  }
+  throw StatusError{HFCR_E_DEVICE, "hit buffer did not converge"};
+}
+
+// Unique stencil keys of the hits of the listed directions into c->st_keys.
+int64_t build_stencils(hfcr_ctx *c, Pair &P, const int *dirs, int nd, DBuf &dst) {
+  int64_t n = 0;
+  for (int q = 0; q < nd; ++q) n += P.hits_n[dirs[q]];
+  if (n == 0) return 0;
+  ensure(c->sk0, n * sizeof(uint64_t));
+  ensure(c->flags, n * sizeof(uint32_t));
+  int64_t off = 0;
+  for (int q = 0; q < nd; ++q) {
+    const int dir = dirs[q];
+    launch_stencil_keys(ptr<uint64_t>(c->hk[dir]), ptr<uint32_t>(c->hv[dir]), P.hits_n[dir], P.hl, P.sl,
+                        ptr<uint64_t>(c->sk0) + off, c->s);
+    off += P.hits_n[dir];
+  }
+  sort_inplace(c, ptr<uint64_t>(c->sk0), nullptr, n, 1 + P.sl.bits_v + P.sl.bits_f);
+  launch_unique_flags(ptr<uint64_t>(c->sk0), n, ~0ull, ptr<uint32_t>(c->flags), c->s);
+  const uint32_t S = scan_count(c, ptr<uint32_t>(c->flags), n);
+  ensure(dst, std::max<int64_t>(S, 1) * sizeof(uint64_t));
+  launch_compact_keys(ptr<uint64_t>(c->sk0), ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), n, ptr<uint64_t>(dst),
+                      c->s);
+  return S;
+}
+
+struct RoundInfo {
+  int64_t S = 0;
+  int nzones = 0;
+  int maxk = 0;
+};
+
+// Constraints, impact zones, solve and update for the stencils in c->st_keys.
+RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
+  RoundInfo info;
+  info.S = S;
+  Counters *dc = ptr<Counters>(c->ctr);
+  const int nvt = P.m[0].nv + P.m[1].nv;
+  const int bits_s = bits_for(S);
+  {
+    Scope t(c, 4);
+    ensure(c->con, S * sizeof(Constraint));
+    launch_constraints(ptr<uint64_t>(c->st_keys), S, P.sl, P.m[0], P.m[1], d, ptr<Constraint>(c->con), c->s);
+  }
+  {
+    Scope t(c, 5);
+    ensure(c->parent, (size_t)std::max(nvt, 1) * sizeof(int));
+    launch_uf_init(ptr<int>(c->parent), nvt, c->s);
+    launch_uf_union(ptr<Constraint>(c->con), S, ptr<int>(c->parent), c->s);
+    ensure(c->zkeys, S * sizeof(uint64_t));
+    ensure(c->zvals, S * sizeof(uint32_t));
+    launch_zone_keys(ptr<Constraint>(c->con), S, ptr<int>(c->parent), bits_s, ptr<uint64_t>(c->zkeys),
+                     ptr<uint32_t>(c->zvals), c->s);
+    sort_inplace(c, ptr<uint64_t>(c->zkeys), ptr<uint32_t>(c->zvals), S, bits_s + bits_for(nvt));
+    ensure(c->flags, S * sizeof(uint32_t));
+    ensure(c->pos, S * sizeof(uint32_t));
+    ensure(c->bsums, scan_block_sums_entries(S) * sizeof(uint32_t));
+    ensure(c->starts, (S + 1) * sizeof(uint32_t));
+    launch_zone_flags(ptr<uint64_t>(c->zkeys), S, bits_s, ptr<uint32_t>(c->flags), c->s);
+    scan_u32(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->bsums), nullptr, c->s);
+    HIP_CHECK(hipMemsetAsync(&dc->maxk, 0, sizeof(uint32_t), c->s));
+    launch_zone_starts(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->starts), &dc->nzones,
+                       &dc->maxk, c->s);
+  }
+  readback(c);
+  info.nzones = (int)c->hctr->nzones;
+  info.maxk = (int)c->hctr->maxk;
+  if (info.maxk > HFCR_MAX_ZONE)
+    throw StatusError{HFCR_E_ZONE_LIMIT, "impact zone of " + std::to_string(info.maxk) + " stencils exceeds " +
+                                             std::to_string(HFCR_MAX_ZONE)};
+  {
+    Scope t(c, 6);
+    const int64_t k = info.maxk;
+    const int64_t stride = 2 * k * k + 5 * k + 8;  // doubles per slot: matrix, C, 3 vectors, 2 int arrays
+    const int64_t budget = (int64_t)1 << 28;       // doubles (2 GiB) across slots
+    int nslots = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)info.nzones, 2048, budget / stride}));
+    ensure(c->solve_scratch, (size_t)nslots * stride * sizeof(double));
+    ensure(c->lambda, S * sizeof(double));
+    SolveArgs a;
+    a.con = ptr<Constraint>(c->con);
+    a.order = ptr<uint32_t>(c->zvals);
+    a.starts = ptr<uint32_t>(c->starts);
+    a.nzones = info.nzones;
+    a.w_a = P.m[0].inv_mass;
+    a.w_b = P.m[1].inv_mass;
+    a.nv_a = P.m[0].nv;
+    a.lambda = ptr<double>(c->lambda);
+    a.scratch = ptr<double>(c->solve_scratch);
+    a.slot_stride = stride;
+    a.nslots = nslots;
+    a.rank_def = &dc->rank_def;
+    a.tau = 1e-12;
+    a.maxk = info.maxk;
+    launch_solve(a, c->s);
+  }
+  {
+    Scope t(c, 7);
+    ensure(c->inc_keys, 4 * S * sizeof(uint64_t));
+    launch_incidence(ptr<Constraint>(c->con), S, bits_s, ptr<uint64_t>(c->inc_keys), c->s);
+    sort_inplace(c, ptr<uint64_t>(c->inc_keys), nullptr, 4 * S, bits_s + 2 + bits_for(nvt));
+    launch_update(ptr<uint64_t>(c->inc_keys), 4 * S, bits_s, ptr<Constraint>(c->con), ptr<double>(c->lambda),
+                  P.m[0], P.m[1], c->s);
+  }
+  P.dirty[0] = P.dirty[1] = true;
+  if (st) st->max_zone = std::max(st->max_zone, info.maxk);
+  return info;
+}
+
+void write_hit_outputs(hfcr_ctx *c, Pair &P, hfcr_result *res, hfcr_stats *st, bool &truncated) {
+  // round-0 hits of every oriented direction, sorted (direction is the key's top bit)
+  int64_t total = 0;
+  for (int q = 0; q < P.ndirs; ++q) total += P.hits_n[P.dirs[q]];
+  if (st) st->hits0 = total;
+  if (res && res->hits && total > 0) {
+    int64_t off = 0;
+    for (int q = 0; q < P.ndirs; ++q) {
+      const int dir = P.dirs[q];
+      int64_t n = P.hits_n[dir];
+      int64_t room = std::max<int64_t>(0, res->hit_cap - off);
+      int64_t m = std::min(n, room);
+      launch_write_hits(ptr<uint64_t>(c->hk[dir]), ptr<uint32_t>(c->hv[dir]), m, P.hl, P.m[0].edges, P.m[1].edges,
+                        res->hits + 5 * off, c->s);
+      off += n;
+    }
+    if (total > res->hit_cap) truncated = true;
+  }
+  const int64_t S0 = build_stencils(c, P, P.dirs, P.ndirs, c->st_out_keys);
+  if (st) st->stencils0 = S0;
+  if (res && res->stencils && S0 > 0) {
+    launch_write_stencils(ptr<uint64_t>(c->st_out_keys), std::min<int64_t>(S0, res->stencil_cap), P.sl,
+                          res->stencils, c->s);
+    if (S0 > res->stencil_cap) truncated = true;
+  }
+}
+
+void setup_pair(hfcr_ctx *c, Pair &P, const hfcr_mesh *a, const hfcr_mesh *b, int orientation,
+                const hfcr_opts *o) {
+  check_mesh(a, "A");
+  check_mesh(b, "B");
+  if (orientation < HFCR_ORIENT_B || orientation > HFCR_ORIENT_BOTH)
+    throw StatusError{HFCR_E_INVALID, "bad orientation"};
+  P.orientation = orientation;
+  if (orientation == HFCR_ORIENT_B) {
+    P.dirs[0] = 0;
+    P.ndirs = 1;
+  } else if (orientation == HFCR_ORIENT_A) {
+    P.dirs[0] = 1;
+    P.ndirs = 1;
+  } else {
+    P.dirs[0] = 0;
+    P.dirs[1] = 1;
+    P.ndirs = 2;
+  }
+  P.tier0 = o->predicate_tier == 0;
+  for (int i = 0; i < 2; ++i) {
+    P.dirty[i] = false;
+    P.has_edges[i] = P.has_bvh[i] = false;
+    P.hit_cap[i] = 4096;
+    P.amb_cap[i] = 4096;
+    P.hits_n[i] = 0;
+  }
+  ensure(c->ctr, sizeof(Counters));
+  reset_counters(c);
+  {
+    Scope t(c, 0);
+    setup_mesh(c, P, 0, a, o->inv_mass_a);
+    setup_mesh(c, P, 1, b, o->inv_mass_b);
+    readback(c);
+    if (c->hctr->err & 1u)
+      throw StatusError{HFCR_E_INVALID, "non-finite or out-of-domain coordinate (|x| must be 0 or in [2^-200, 2^200])"};
+    if (c->hctr->err & 2u) throw StatusError{HFCR_E_INVALID, "triangle index out of range"};
+    for (int i = 0; i < 2; ++i) {
+      float m;
+      std::memcpy(&m, &c->hctr->maxabs[i], sizeof(float));
+      P.m[i].small_coords = m <= 4294967296.0f;
+    }
+    for (int q = 0; q < P.ndirs; ++q) {
+      const int dir = P.dirs[q];
+      const int ei = dir == 0 ? 0 : 1, fi = dir == 0 ? 1 : 0;
+      if (!P.has_edges[ei]) build_edges(c, P, ei);
+      if (!P.has_bvh[fi]) build_bvh(c, P, fi);
+    }
+  }
+  int64_t maxe = std::max(P.m[0].ne, P.m[1].ne), maxf = std::max(P.m[0].nt, P.m[1].nt);
+  int64_t maxv = std::max(P.m[0].nv, P.m[1].nv);
+  P.hl.bits_f = bits_for(maxf);
+  P.hl.bits_e = bits_for(maxe);
+  P.sl.bits_f = P.hl.bits_f;
+  P.sl.bits_v = bits_for(maxv);
+}
+
+void finish_timing(hfcr_ctx *c, hfcr_stats *st) {
+  if (!c->timers.empty()) {
+    HIP_CHECK(hipStreamSynchronize(c->s));
+    for (auto &t : c->timers) {
+      float ms = 0.f;
+      HIP_CHECK(hipEventElapsedTime(&ms, t.a, t.b));
+      if (st) {
+        st->stage_ms[t.stage] += ms;
+        st->stage_calls[t.stage] += 1;
+      }
+      c->free_events.push_back(t.a);
+      c->free_events.push_back(t.b);
+    }
+    c->timers.clear();
+  }
+}
+
+template <typename F>
+hfcr_status guarded(hfcr_ctx *c, F &&body) {
+  if (!c) return HFCR_E_INVALID;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  hfcr_status st = HFCR_OK;
+  try {
+    HIP_CHECK(hipSetDevice(c->device));
+    st = body();
+  } catch (const StatusError &e) {
+    c->err = e.msg;
+    st = e.st;
+  } catch (const HipError &e) {
+    c->err = std::string(e.what) + ": " + hipGetErrorString(e.e);
+    st = HFCR_E_DEVICE;
+  }
+  // release timers on error paths too
+  for (auto &t : c->timers) {
+    c->free_events.push_back(t.a);
+    c->free_events.push_back(t.b);
+  }
+  c->timers.clear();
+  (void)hipSetDevice(prev);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hfcr_default_opts(hfcr_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_rounds = 256;
+  o->both_mode = HFCR_BOTH_ALTERNATE;
+  o->predicate_tier = 0;
+  o->round_offset = 0;
+}
+
+hfcr_status hfcr_create(hfcr_ctx **out, int device) {
+  if (!out) return HFCR_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return HFCR_E_DEVICE;
+  hfcr_ctx *c = new hfcr_ctx();
+  c->device = device;
+  hfcr_status st = guarded(c, [&]() -> hfcr_status {
+    void *h = nullptr;
+    HIP_CHECK(hipHostMalloc(&h, sizeof(Counters), hipHostMallocDefault));
+    c->hctr = reinterpret_cast<Counters *>(h);
+    ensure(c->ctr, sizeof(Counters), true);
+    return HFCR_OK;
+  });
+  if (st != HFCR_OK) {
+    hfcr_destroy(c);
+    return st;
+  }
+  *out = c;
+  return HFCR_OK;
+}
+
+void hfcr_destroy(hfcr_ctx *c) {
+  if (!c) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  DBuf *all[] = {&c->sk0, &c->sk1, &c->sv0, &c->sv1, &c->hist, &c->flags, &c->pos, &c->bsums, &c->st_keys,
+                 &c->st_out_keys, &c->con, &c->parent, &c->zkeys, &c->zvals, &c->starts, &c->lambda, &c->inc_keys,
+                 &c->solve_scratch, &c->ctr};
+  for (DBuf *b : all)
+    if (b->p) (void)hipFree(b->p);
+  for (int i = 0; i < 2; ++i) {
+    DBuf *m[] = {&c->x64[i], &c->x32[i], &c->edges[i], &c->qedges[i], &c->leaf_tri[i], &c->nodes[i],
+                 &c->leaf_parent[i], &c->counters_n[i], &c->root_box[i], &c->codes[i], &c->scene_box[i],
+                 &c->hk[i], &c->hv[i], &c->amb[i]};
+    for (DBuf *b : m)
+      if (b->p) (void)hipFree(b->p);
+  }
+  if (c->hctr) (void)hipHostFree(c->hctr);
+  for (hipEvent_t e : c->free_events) (void)hipEventDestroy(e);
+  (void)hipSetDevice(prev);
+  delete c;
+}
+
+const char *hfcr_last_error(const hfcr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+hfcr_status hfcr_detect(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, int32_t orientation,
+                        const hfcr_opts *opts, hfcr_result *res, void *stream) {
+  return guarded(c, [&]() -> hfcr_status {
+    hfcr_opts o;
+    hfcr_default_opts(&o);
+    if (opts) o = *opts;
+    c->s = (hipStream_t)stream;
+    hfcr_stats *st = res ? res->stats : nullptr;
+    if (st) std::memset(st, 0, sizeof(*st));
+    c->timing = (o.flags & HFCR_FLAG_TIMING) != 0;
+    Pair P;
+    setup_pair(c, P, a, b, orientation, &o);
+    for (int q = 0; q < P.ndirs; ++q) detect_dir(c, P, P.dirs[q]);
+    bool truncated = false;
+    write_hit_outputs(c, P, res, st, truncated);
+    readback(c);
+    if (st) {
+      st->candidates = (int64_t)c->hctr->cand;
+      st->exact_tests = (int64_t)c->hctr->exact;
+      st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
+      st->converged = st->hits0 == 0;
+      st->residual_hits = st->hits0;
+    }
+    finish_timing(c, st);
+    return truncated ? HFCR_E_CAPACITY : HFCR_OK;
+  });
+}
+
+hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, int32_t orientation, double d,
+                         const hfcr_opts *opts, hfcr_result *res, void *stream) {
+  return guarded(c, [&]() -> hfcr_status {
+    hfcr_opts o;
+    hfcr_default_opts(&o);
+    if (opts) o = *opts;
+    if (!(d >= 0.0) || !std::isfinite(d)) throw StatusError{HFCR_E_INVALID, "d must be finite and >= 0"};
+    if (o.max_rounds < 0) throw StatusError{HFCR_E_INVALID, "max_rounds must be >= 0"};
+    if (o.both_mode != HFCR_BOTH_ALTERNATE && o.both_mode != HFCR_BOTH_SIMULTANEOUS)
+      throw StatusError{HFCR_E_INVALID, "bad both_mode"};
+    c->s = (hipStream_t)stream;
+    hfcr_stats *st = res ? res->stats : nullptr;
+    if (st) std::memset(st, 0, sizeof(*st));
+    c->timing = (o.flags & HFCR_FLAG_TIMING) != 0;
+    Pair P;
+    setup_pair(c, P, a, b, orientation, &o);
+    const bool alternate = orientation == HFCR_ORIENT_BOTH && o.both_mode == HFCR_BOTH_ALTERNATE;
+    bool converged = false, truncated = false;
+    int rounds = 0;
+    int64_t residual = 0;
+    hfcr_status status = HFCR_OK;
+    try {
+      for (int r = 0; r <= o.max_rounds; ++r) {
+        int act[2], nact = 0;
+        int64_t nhits = 0;
+        if (alternate) {
+          const int first = (int)(((int64_t)r + o.round_offset) & 1);
+          const int64_t nf = detect_dir(c, P, first);
+          int64_t ns = 0;
+          if (r == 0 || nf == 0) ns = detect_dir(c, P, 1 - first);
+          else P.hits_n[1 - first] = 0;
+          if (r == 0) write_hit_outputs(c, P, res, st, truncated);
+          if (nf > 0) {
+            act[nact++] = first;
+            nhits = nf;
+          } else if (ns > 0) {
+            act[nact++] = 1 - first;
+            nhits = ns;
+          }
+        } else {
+          for (int q = 0; q < P.ndirs; ++q) {
+            const int dir = P.dirs[q];
+            const int64_t n = detect_dir(c, P, dir);
+            if (n > 0) {
+              act[nact++] = dir;
+              nhits += n;
+            }
+          }
+          if (r == 0) write_hit_outputs(c, P, res, st, truncated);
+        }
+        if (st && r < HFCR_STAT_ROUNDS) st->round_hits[r] = (int32_t)nhits;
+        if (nact == 0) {
+          converged = true;
+          break;
+        }
+        if (r == o.max_rounds) {
+          residual = nhits;
+          if (alternate && nact == 1 && P.hits_n[1 - act[0]] == 0 && act[0] == (int)(((int64_t)r + o.round_offset) & 1))
+            residual += detect_dir(c, P, 1 - act[0]);
+          break;
+        }
+        const int64_t S = build_stencils(c, P, act, nact, c->st_keys);
+        RoundInfo info = respond(c, P, S, d, st);
+        if (st && r < HFCR_STAT_ROUNDS) {
+          st->round_stencils[r] = (int32_t)S;
+          st->round_zones[r] = info.nzones;
+          st->round_max_zone[r] = info.maxk;
+        }
+        ++rounds;
+      }
+    } catch (const StatusError &e) {
+      if (e.st != HFCR_E_ZONE_LIMIT) throw;
+      c->err = e.msg;
+      status = HFCR_E_ZONE_LIMIT;
+    }
+    if (res) {
+      launch_write_positions(P.m[0], res->pos_a_out, c->s);
+      launch_write_positions(P.m[1], res->pos_b_out, c->s);
+    }
+    readback(c);
+    if (st) {
+      st->rounds = rounds;
+      st->converged = converged ? 1 : 0;
+      st->residual_hits = converged ? 0 : residual;
+      st->candidates = (int64_t)c->hctr->cand;
+      st->exact_tests = (int64_t)c->hctr->exact;
+      st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
+      st->rank_deficient = c->hctr->rank_def;
+    }
+    finish_timing(c, st);
+    if (status != HFCR_OK) return status;
+    if (truncated) return HFCR_E_CAPACITY;
+    return converged ? HFCR_OK : HFCR_NOT_CONVERGED;
+  });
+}
+
+hfcr_status hfcr_test_orient(hfcr_ctx *c, const double *pts, int64_t n, int32_t tier, int32_t *out, void *stream) {
+  return guarded(c, [&]() -> hfcr_status {
+    if (n < 0 || tier < 0 || tier > 2 || (n > 0 && (!pts || !out)))
+      throw StatusError{HFCR_E_INVALID, "bad arguments"};
+    launch_test_orient(pts, n, tier, out, (hipStream_t)stream);
+    HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    return HFCR_OK;
+  });
+}
+
+}  // extern "C"

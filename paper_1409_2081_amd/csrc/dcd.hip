@@ -1,0 +1,302 @@
+// Discrete collision detection: every E-F intersection between the edges of
+// one mesh (queries, in Morton order) and the faces of the other (leaves of
+// its BVH).
+//
+// One lane per query edge walks the face BVH depth-first; its stack lives in
+// LDS (one column per lane, so lanes of a wave hit distinct banks).  Every
+// leaf whose box overlaps the segment's box is a candidate and goes through
+// the filtered narrow phase inline.  Hits and undecided candidates are
+// appended with one atomic per wavefront (ballot, popcount, prefix by mbcnt);
+// their order is made deterministic afterwards by sorting the keys.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "predicates.hpp"
+
+namespace hfcr {
+
+constexpr int kTravBlock = 128;
+constexpr int kStack = 64;  // tree depth <= 30 Morton bits + 24 index bits + 1
+
+__device__ inline uint64_t lanemask_lt() {
+  const unsigned lane = __lane_id();
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Append for the lanes where pred holds; returns the slot (or ~0u).
+__device__ inline uint32_t wave_append(uint32_t *counter, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return ~0u;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if ((int)__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = (uint32_t)__shfl((int)base, leader);
+  return pred ? base + (uint32_t)__popcll(m & lanemask_lt()) : ~0u;
+}
+
+__device__ inline bool box_overlap(const float lo[3], const float hi[3], float l0, float l1, float l2, float h0,
+                                   float h1, float h2) {
+  return lo[0] <= h0 && l0 <= hi[0] && lo[1] <= h1 && l1 <= hi[1] && lo[2] <= h2 && l2 <= hi[2];
+}
+
+struct TravArgs {
+  const int4 *qedges;
+  int ne;
+  const double *ex64;
+  const float *ex32;
+  int env;
+  const int4 *leaf_tri;
+  const BvhNode *nodes;
+  const float *root_box;
+  int nt;
+  const double *fx64;
+  const float *fx32;
+  int fnv;
+  int dir;
+  HitLayout lay;
+  DcdOut out;
+};
+
+template <bool F32>
+__device__ inline void load_point(const double *x64, const float *x32, int nv, int i, P3f &pf, P3d &pd) {
+  pd.x = x64[i];
+  pd.y = x64[(int64_t)nv + i];
+  pd.z = x64[2 * (int64_t)nv + i];
+  if (F32) {
+    pf.x = x32[i];
+    pf.y = x32[(int64_t)nv + i];
+    pf.z = x32[2 * (int64_t)nv + i];
+  }
+}
+
+// Narrow phase for one candidate: returns 0/1/2, or kHitUnsure after both filters.
+template <bool F32, bool TIER0>
+__device__ inline int narrow(const TravArgs &A, P3f pf, P3f qf, P3d pd, P3d qd, int4 t, unsigned long long &unsure32) {
+  P3f af, bf, cf;
+  P3d ad, bd, cd;
+  if (TIER0) {
+    load_point<true>(A.fx64, A.fx32, A.fnv, t.x, af, ad);
+    load_point<true>(A.fx64, A.fx32, A.fnv, t.y, bf, bd);
+    load_point<true>(A.fx64, A.fx32, A.fnv, t.z, cf, cd);
+    int r = ef_test_f32(pf, qf, af, bf, cf);
+    if (r != kHitUnsure) return r;
+    ++unsure32;
+  } else {
+    load_point<false>(A.fx64, A.fx32, A.fnv, t.x, af, ad);
+    load_point<false>(A.fx64, A.fx32, A.fnv, t.y, bf, bd);
+    load_point<false>(A.fx64, A.fx32, A.fnv, t.z, cf, cd);
+  }
+  return ef_test_f64<false>(pd, qd, ad, bd, cd);
+}
+
+template <bool F32, bool TIER0>
+__global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs A) {
+  __shared__ int stack[kStack][kTravBlock];
+  const int tid = threadIdx.x;
+  const int qi = blockIdx.x * kTravBlock + tid;
+  const bool valid = qi < A.ne;
+  unsigned long long ncand = 0, unsure32 = 0;
+  int4 qe = valid ? A.qedges[qi] : make_int4(0, 0, 0, 0);
+  P3f pf{}, qf{};
+  P3d pd{}, qd{};
+  float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  if (valid) {
+    load_point<F32>(A.ex64, A.ex32, A.env, qe.x, pf, pd);
+    load_point<F32>(A.ex64, A.ex32, A.env, qe.y, qf, qd);
+    if (F32) {
+      lo[0] = fminf(pf.x, qf.x); hi[0] = fmaxf(pf.x, qf.x);
+      lo[1] = fminf(pf.y, qf.y); hi[1] = fmaxf(pf.y, qf.y);
+      lo[2] = fminf(pf.z, qf.z); hi[2] = fmaxf(pf.z, qf.z);
+    } else {
+      lo[0] = __double2float_rd(fmin(pd.x, qd.x)); hi[0] = __double2float_ru(fmax(pd.x, qd.x));
+      lo[1] = __double2float_rd(fmin(pd.y, qd.y)); hi[1] = __double2float_ru(fmax(pd.y, qd.y));
+      lo[2] = __double2float_rd(fmin(pd.z, qd.z)); hi[2] = __double2float_ru(fmax(pd.z, qd.z));
+    }
+  }
+  const float *rb = A.root_box;
+  bool alive = valid && A.nt > 0 && box_overlap(lo, hi, rb[0], rb[1], rb[2], rb[3], rb[4], rb[5]);
+  // A single face has no internal node: test it directly.
+  int pending_leaf = (alive && A.nt == 1) ? 0 : -1;
+  if (A.nt == 1) alive = false;
+  int node = 0, sp = 0;
+  const uint64_t dir_bits = (uint64_t)A.dir << (A.lay.bits_e + A.lay.bits_f);
+  while (true) {
+    int leaf_a = pending_leaf, leaf_b = -1;
+    pending_leaf = -1;
+    if (alive) {
+      const BvhNode nd = A.nodes[node];
+      const bool o0 = box_overlap(lo, hi, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
+      const bool o1 = box_overlap(lo, hi, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
+      const int c0 = nd.d.x, c1 = nd.d.y;
+      bool i0 = o0 && c0 >= 0, i1 = o1 && c1 >= 0;
+      if (o0 && c0 < 0) leaf_a = ~c0;
+      if (o1 && c1 < 0) leaf_b = ~c1;
+      if (i0 && i1) {
+        if (sp >= kStack) {
+          atomicOr(A.out.overflow, 1);
+          alive = false;
+        } else {
+          stack[sp++][tid] = c1;
+          node = c0;
+        }
+      } else if (i0) {
+        node = c0;
+      } else if (i1) {
+        node = c1;
+      } else if (sp > 0) {
+        node = stack[--sp][tid];
+      } else {
+        alive = false;
+      }
+    }
+    // narrow phase of up to two leaves found at this step
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int leaf = k == 0 ? leaf_a : leaf_b;
+      int res = 0;
+      int4 t = make_int4(0, 0, 0, 0);
+      if (leaf >= 0) {
+        t = A.leaf_tri[leaf];
+        ++ncand;
+        res = narrow<F32, TIER0>(A, pf, qf, pd, qd, t, unsure32);
+      }
+      const bool is_hit = res == 1 || res == 2;
+      const uint32_t slot = wave_append(A.out.count, is_hit);
+      if (is_hit && slot < A.out.cap) {
+        A.out.keys[slot] = dir_bits | ((uint64_t)qe.z << A.lay.bits_f) | (uint32_t)t.w;
+        A.out.vals[slot] = (uint32_t)(res == 1 ? qe.x : qe.y);
+      }
+      const bool is_amb = res == kHitUnsure;
+      const uint32_t aslot = wave_append(A.out.amb_count, is_amb);
+      if (is_amb && aslot < A.out.amb_cap) A.out.amb[aslot] = make_uint2((uint32_t)qi, (uint32_t)leaf);
+    }
+    if (!__any(alive)) break;
+  }
+  // one counter update per wave
+  for (int off = 32; off > 0; off >>= 1) {
+    ncand += __shfl_xor(ncand, off);
+    unsure32 += __shfl_xor(unsure32, off);
+  }
+  if (__lane_id() == 0) {
+    if (ncand) atomicAdd(A.out.cand, ncand);
+    if (unsure32) atomicAdd(A.out.f32_unsure, unsure32);
+  }
+}
+
+static TravArgs make_args(const MeshDev &E, const MeshDev &F, int dir, HitLayout lay, const DcdOut &out) {
+  TravArgs a;
+  a.qedges = E.qedges;
+  a.ne = E.ne;
+  a.ex64 = E.x64;
+  a.ex32 = E.x32;
+  a.env = E.nv;
+  a.leaf_tri = F.leaf_tri;
+  a.nodes = F.nodes;
+  a.root_box = F.root_box;
+  a.nt = F.nt;
+  a.fx64 = F.x64;
+  a.fx32 = F.x32;
+  a.fnv = F.nv;
+  a.dir = dir;
+  a.lay = lay;
+  a.out = out;
+  return a;
+}
+
+void launch_traverse(const MeshDev &E, const MeshDev &F, int dir, bool tier0, HitLayout lay, const DcdOut &out,
+                     hipStream_t s) {
+  if (E.ne <= 0 || F.nt <= 0) return;
+  TravArgs a = make_args(E, F, dir, lay, out);
+  const unsigned grid = grid_for(E.ne, kTravBlock);
+  const bool f32 = E.f32 && F.f32 && E.x32 && F.x32;
+  if (f32 && tier0 && E.small_coords && F.small_coords)
+    k_traverse<true, true><<<grid, kTravBlock, 0, s>>>(a);
+  else if (f32)
+    k_traverse<true, false><<<grid, kTravBlock, 0, s>>>(a);
+  else
+    k_traverse<false, false><<<grid, kTravBlock, 0, s>>>(a);
+}
+
+// ------------------------------------------------------------ exact tier
+// Grid-stride over the undecided candidates (count read on the device).
+__global__ __launch_bounds__(64) void k_exact(TravArgs A) {
+  const uint32_t namb = *A.out.amb_count;
+  const uint32_t n = namb < A.out.amb_cap ? namb : (uint32_t)A.out.amb_cap;
+  const uint64_t dir_bits = (uint64_t)A.dir << (A.lay.bits_e + A.lay.bits_f);
+  unsigned long long nex = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint2 item = A.out.amb[i];
+    int4 qe = A.qedges[item.x];
+    int4 t = A.leaf_tri[item.y];
+    P3f dummy;
+    P3d p, q, a, b, c;
+    load_point<false>(A.ex64, nullptr, A.env, qe.x, dummy, p);
+    load_point<false>(A.ex64, nullptr, A.env, qe.y, dummy, q);
+    load_point<false>(A.fx64, nullptr, A.fnv, t.x, dummy, a);
+    load_point<false>(A.fx64, nullptr, A.fnv, t.y, dummy, b);
+    load_point<false>(A.fx64, nullptr, A.fnv, t.z, dummy, c);
+    int ne = 0;
+    int res = ef_test_f64<true>(p, q, a, b, c, &ne);
+    nex += (unsigned long long)ne;
+    if (res == 1 || res == 2) {
+      uint32_t slot = atomicAdd(A.out.count, 1u);
+      if (slot < A.out.cap) {
+        A.out.keys[slot] = dir_bits | ((uint64_t)qe.z << A.lay.bits_f) | (uint32_t)t.w;
+        A.out.vals[slot] = (uint32_t)(res == 1 ? qe.x : qe.y);
+      }
+    }
+  }
+  if (nex) atomicAdd(A.out.exact, nex);
+}
+
+void launch_exact(const MeshDev &E, const MeshDev &F, int dir, HitLayout lay, const DcdOut &out, hipStream_t s) {
+  if (E.ne <= 0 || F.nt <= 0) return;
+  TravArgs a = make_args(E, F, dir, lay, out);
+  k_exact<<<256, 64, 0, s>>>(a);
+}
+
+// ------------------------------------------------------------ hit output
+__global__ void k_write_hits(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t n,
+                             HitLayout lay, const int2 *__restrict__ ea, const int2 *__restrict__ eb, int32_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t k = keys[i];
+  int f = (int)(k & ((1ull << lay.bits_f) - 1));
+  int e = (int)((k >> lay.bits_f) & ((1ull << lay.bits_e) - 1));
+  int dir = (int)(k >> (lay.bits_f + lay.bits_e));
+  int2 uv = dir == 0 ? ea[e] : eb[e];
+  int32_t *o = out + 5 * i;
+  o[0] = dir;
+  o[1] = uv.x;
+  o[2] = uv.y;
+  o[3] = f;
+  o[4] = (int32_t)vals[i];
+}
+
+void launch_write_hits(const uint64_t *keys, const uint32_t *vals, int64_t n, HitLayout lay, const int2 *ea,
+                       const int2 *eb, int32_t *out, hipStream_t s) {
+  if (n > 0) k_write_hits<<<grid_for(n, 256), 256, 0, s>>>(keys, vals, n, lay, ea, eb, out);
+}
+
+// ------------------------------------------------------ predicate probe
+// Signs of orient(a,b,c,p) for n quadruples pts[n][4][3]: tier 0 = float32
+// filter (may be kUnsure), 1 = float64 filter (may be kUnsure), 2 = exact.
+__global__ void k_test_orient(const double *pts, int64_t n, int tier, int32_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *q = pts + 12 * i;
+  int s;
+  if (tier == 0)
+    s = filtered_sign_f32((float)q[0], (float)q[1], (float)q[2], (float)q[3], (float)q[4], (float)q[5],
+                          (float)q[6], (float)q[7], (float)q[8], (float)q[9], (float)q[10], (float)q[11]);
+  else if (tier == 1)
+    s = filtered_sign_f64(q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11]);
+  else
+    s = exact_sign(q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10], q[11]);
+  out[i] = s;
+}
+
+void launch_test_orient(const double *pts, int64_t n, int tier, int32_t *out, hipStream_t s) {
+  if (n > 0) k_test_orient<<<grid_for(n, 256), 256, 0, s>>>(pts, n, tier, out);
+}
+
+}  // namespace hfcr

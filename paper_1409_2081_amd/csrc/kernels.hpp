@@ -1,0 +1,95 @@
+// Host-side launchers of every kernel (one translation unit each family).
+#pragma once
+
+#include "common.hpp"
+
+namespace hfcr {
+
+// bvh.hip
+void launch_ingest(const MeshDev &m, unsigned *err, unsigned *maxabs, hipStream_t s);
+void launch_edge_keys(const MeshDev &m, uint64_t *keys, hipStream_t s);
+void launch_unique_flags(const uint64_t *keys, int64_t n, uint64_t invalid_from, uint32_t *flags,
+                         hipStream_t s);
+void launch_compact_edges(const uint64_t *keys, const uint32_t *flags, const uint32_t *pos, int64_t n,
+                          int2 *edges, hipStream_t s);
+void launch_bounds(const MeshDev &m, float *box, hipStream_t s);
+void launch_edge_morton(const MeshDev &m, const float *box, uint64_t *keys, hipStream_t s);
+void launch_make_qedges(const MeshDev &m, const uint64_t *keys, hipStream_t s);
+void launch_face_morton(const MeshDev &m, const float *box, uint64_t *keys, hipStream_t s);
+void launch_leaf_tri(const MeshDev &m, const uint64_t *keys, uint32_t *codes, hipStream_t s);
+void launch_build_tree(const MeshDev &m, const uint32_t *codes, hipStream_t s);
+void launch_refit(const MeshDev &m, hipStream_t s);
+
+// dcd.hip
+struct HitLayout {
+  int bits_f;  // face index bits
+  int bits_e;  // edge index bits
+};
+struct DcdOut {
+  uint64_t *keys;        // hit keys (dir, e, f)
+  uint32_t *vals;        // x0 (local vertex id in the edge mesh)
+  uint32_t *count;       // device counter
+  int64_t cap;
+  uint2 *amb;            // (query index, leaf index) needing the exact tier
+  uint32_t *amb_count;   // device counter
+  int64_t amb_cap;
+  unsigned long long *cand;     // narrow-phase tests
+  unsigned long long *f32_unsure;
+  unsigned long long *exact;    // exact-tier tests
+  int *overflow;         // traversal stack overflow flag
+};
+void launch_traverse(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, bool tier0, HitLayout lay,
+                     const DcdOut &out, hipStream_t s);
+void launch_exact(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, HitLayout lay, const DcdOut &out,
+                  hipStream_t s);
+void launch_write_hits(const uint64_t *keys, const uint32_t *vals, int64_t n, HitLayout lay, const int2 *edges_a,
+                       const int2 *edges_b, int32_t *out, hipStream_t s);
+void launch_test_orient(const double *pts, int64_t n, int tier, int32_t *out, hipStream_t s);
+
+// response.hip
+struct StencilLayout {
+  int bits_f;  // face index bits
+  int bits_v;  // local vertex bits
+};
+void launch_stencil_keys(const uint64_t *hit_keys, const uint32_t *hit_vals, int64_t n, HitLayout hl,
+                         StencilLayout sl, uint64_t *out, hipStream_t s);
+void launch_compact_keys(const uint64_t *keys, const uint32_t *flags, const uint32_t *pos, int64_t n,
+                         uint64_t *out, hipStream_t s);
+void launch_write_stencils(const uint64_t *keys, int64_t n, StencilLayout sl, int32_t *out, hipStream_t s);
+
+struct Constraint {
+  double4 n;   // unit normal (x, y, z) and r = D - d in w
+  int4 v;      // global vertex ids x0, x1, x2, x3
+};
+void launch_constraints(const uint64_t *st_keys, int64_t S, StencilLayout sl, const MeshDev &A, const MeshDev &B,
+                        double d, Constraint *con, hipStream_t s);
+void launch_uf_init(int *parent, int n, hipStream_t s);
+void launch_uf_union(const Constraint *con, int64_t S, int *parent, hipStream_t s);
+void launch_zone_keys(const Constraint *con, int64_t S, const int *parent, int bits_s, uint64_t *keys,
+                      uint32_t *vals, hipStream_t s);
+void launch_zone_flags(const uint64_t *keys, int64_t S, int bits_s, uint32_t *flags, hipStream_t s);
+void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, uint32_t *starts,
+                        uint32_t *nzones_out, uint32_t *maxk_out, hipStream_t s);
+
+struct SolveArgs {
+  const Constraint *con;
+  const uint32_t *order;    // stencil ids grouped by zone
+  const uint32_t *starts;   // [nzones + 1]
+  int nzones;
+  const double *w_a, *w_b;  // inverse masses or null
+  int nv_a;
+  double *lambda;           // [S]
+  double *scratch;          // per-slot 2*maxk^2 doubles
+  int64_t slot_stride;      // doubles per slot
+  int nslots;
+  int *rank_def;            // count of rank-deficient zones
+  double tau;
+  int maxk;                 // largest zone
+};
+void launch_solve(const SolveArgs &a, hipStream_t s);
+void launch_incidence(const Constraint *con, int64_t S, int bits_s, uint64_t *keys, hipStream_t s);
+void launch_update(const uint64_t *keys, int64_t n, int bits_s, const Constraint *con, const double *lambda,
+                   MeshDev &A, MeshDev &B, hipStream_t s);
+void launch_write_positions(const MeshDev &m, void *out, hipStream_t s);
+
+}  // namespace hfcr

@@ -94,7 +94,10 @@ def adversarial_points(rng, n):
         elif kind == 1:  # coplanar, then nudged by one ulp
             s, t = rng.integers(-4, 5, 2) / 4.0
             p = a + s * (b - a) + t * (c - a)
-            p = np.nextafter(p, p + rng.choice([-1.0, 1.0], 3))
+            step = rng.choice([-1.0, 1.0], 3)
+            # one ulp for nonzero coordinates; an exact zero moves to +-2^-100,
+            # the inputs' domain being 0 or magnitudes in [2^-200, 2^200]
+            p = np.where(p != 0, np.nextafter(p, p + step), step * 2.0 ** -100)
         elif kind == 2:  # large offset: differences lose bits in floating point
             off = rng.uniform(1e6, 1e8, 3)
             s, t = rng.integers(-4, 5, 2) / 4.0
@@ -111,4 +114,7 @@ def adversarial_points(rng, n):
             s, t = rng.uniform(-1, 1, 2)
             p = (a + s * (b - a) + t * (c - a)).astype(np.float32).astype(float)
         pts.append(np.stack([a, b, c, p]))
-    return np.array(pts)
+    pts = np.array(pts)
+    mag = np.abs(pts)
+    assert np.all((mag == 0) | ((mag >= 2.0 ** -200) & (mag <= 2.0 ** 200)))
+    return pts
