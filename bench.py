@@ -56,7 +56,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rounds", type=int, default=12)
-    ap.add_argument("--cpu-sample-rounds", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU-oracle sample length (whole steps are repeated)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -136,6 +137,7 @@ def main():
         "p50_ms": pct(50), "p99_ms": pct(99),
         "converged": s0["converged"], "rounds": s0["rounds"], "residual_hits": s0["residual_hits"],
         "hits0": s0["hits0"], "candidates_per_step": cand / args.steps,
+        "node_visits_per_step": sum(s.get("node_visits", 0) for s in stats) / args.steps,
         "exact_tests_per_step": s0["exact_tests"], "f32_unsure_per_step": s0["f32_ambiguous"],
         "max_zone": s0["max_zone"], "stage_ms_per_step": stage_ms, "stage_launches_per_step": stage_calls,
         "dominant_stage": dominant,
@@ -147,14 +149,20 @@ def main():
         nthreads = min(os.cpu_count() or 1, 16)
         oracle.lib()
         t = time.perf_counter()
-        o = oracle.resolve_pair(pair, nthreads=nthreads, max_rounds=args.cpu_sample_rounds)
-        dt = time.perf_counter() - t
+        n_steps, cand_cpu = 0, 0
+        while True:
+            o = oracle.resolve_pair(pair, nthreads=nthreads, max_rounds=args.rounds)
+            n_steps += 1
+            cand_cpu += o["candidates"]
+            dt = time.perf_counter() - t
+            if dt >= args.cpu_seconds:
+                break
         out["cpu_baseline"] = {
-            "value": o["candidates"] / dt, "unit": "E-F tests/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"oracle resolve of the same pair with max_rounds={args.cpu_sample_rounds} "
-                      f"({o['rounds']} responses, {o['candidates']} candidate tests, {dt:.1f} s; "
-                      "brute-force E-F DCD with box rejection, OpenMP over edges)",
-            "seconds": dt,
+            "value": cand_cpu / dt, "unit": "E-F tests/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n_steps} oracle resolves of the same pair and round budget "
+                      f"({o['rounds']} responses each, {cand_cpu} candidate tests, {dt:.1f} s; "
+                      "brute-force E-F DCD with box rejection and OpenMP over edges, numpy zone solves)",
+            "seconds": dt, "ms_per_step": 1e3 * dt / n_steps,
         }
     print(json.dumps(out))
 

@@ -136,6 +136,11 @@ typedef struct {
   int64_t f32_ambiguous;     /* tests the float32 filter could not settle    */
   int32_t max_zone;          /* largest impact zone seen (stencils)          */
   int32_t rank_deficient;    /* zones solved in the least-squares sense      */
+  int64_t node_visits;       /* BVH nodes fetched by the traversals          */
+  int32_t pivoted_zones;     /* zones solved by the pivoted fallback (a zone
+                                whose unpivoted pivots fell below 1e-6 of
+                                its largest diagonal entry)                 */
+  int32_t reserved_stat;
   double stage_ms[HFCR_STAGES];     /* with HFCR_FLAG_TIMING, else 0        */
   int32_t stage_calls[HFCR_STAGES]; /* timed intervals per stage            */
   int32_t round_hits[HFCR_STAT_ROUNDS];

@@ -376,6 +376,7 @@ def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 
     hits0 = np.zeros((0, 5), np.int32)
     converged = False
     status = "not_converged"
+    residual_now = 0
     r = 0
 
     def det(direction):
@@ -401,6 +402,11 @@ def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 
             converged = True
             break
         if r == max_rounds:
+            # residual over every oriented direction, reusing this round's detections
+            if orientation == ORIENT_BOTH and mode == MODE_ALTERNATE:
+                residual_now = len(h1) + (len(h2) if (r == 0 or len(h1) == 0) else len(det(1 - first)))
+            else:
+                residual_now = len(active)
             break
         st = stencils(active)
         try:
@@ -425,7 +431,7 @@ def resolve(pos_a, tri_a, pos_b, tri_b, orientation: int = ORIENT_B, d: float = 
     if converged:
         status = "ok"
     elif status != "zone_limit":
-        residual = sum(len(det(dr)) for dr in oriented)
+        residual = residual_now
     out_t = np.float32 if dtype == "f32" else np.float64
     return {
         "pos_a": xa.astype(out_t), "pos_b": xb.astype(out_t),

@@ -62,6 +62,8 @@ class Stats(ctypes.Structure):
                 ("stencils0", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("exact_tests", ctypes.c_int64), ("f32_ambiguous", ctypes.c_int64),
                 ("max_zone", ctypes.c_int32), ("rank_deficient", ctypes.c_int32),
+                ("node_visits", ctypes.c_int64), ("pivoted_zones", ctypes.c_int32),
+                ("reserved_stat", ctypes.c_int32),
                 ("stage_ms", ctypes.c_double * STAGES), ("stage_calls", ctypes.c_int32 * STAGES),
                 ("round_hits", ctypes.c_int32 * STAT_ROUNDS),
                 ("round_stencils", ctypes.c_int32 * STAT_ROUNDS),
@@ -75,7 +77,8 @@ class Stats(ctypes.Structure):
             "residual_hits": self.residual_hits, "hits0": self.hits0, "stencils0": self.stencils0,
             "candidates": self.candidates, "exact_tests": self.exact_tests,
             "f32_ambiguous": self.f32_ambiguous, "max_zone": self.max_zone,
-            "rank_deficient": self.rank_deficient,
+            "rank_deficient": self.rank_deficient, "node_visits": self.node_visits,
+            "pivoted_zones": self.pivoted_zones,
             "stage_ms": {STAGE_NAMES[i]: self.stage_ms[i] for i in range(STAGES)},
             "stage_calls": {STAGE_NAMES[i]: self.stage_calls[i] for i in range(STAGES)},
             "round_hits": list(self.round_hits[:n]), "round_stencils": list(self.round_stencils[:n]),

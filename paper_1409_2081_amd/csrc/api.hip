@@ -32,10 +32,12 @@ struct Counters {
   uint32_t nzones;
   uint32_t maxk;
   int32_t rank_def;
-  uint32_t pad[3];
+  int32_t pivoted;
+  uint32_t pad[2];
   unsigned long long cand;
   unsigned long long f32_unsure;
   unsigned long long exact;
+  unsigned long long visits;
 };
 
 struct Timer {
@@ -62,7 +64,7 @@ struct hfcr_ctx {
   hipStream_t s = nullptr;
   // per mesh
   DBuf x64[2], x32[2], edges[2], qedges[2], leaf_tri[2], nodes[2], leaf_parent[2], counters_n[2], root_box[2],
-      codes[2], scene_box[2];
+      codes[2], scene_box[2], topo[2];
   // detection
   DBuf hk[2], hv[2], amb[2];
   // generic sort / scan scratch
@@ -154,6 +156,7 @@ struct Scope {  // times the launches issued during its lifetime
 };
 
 void readback(hfcr_ctx *c) {
+  HIP_CHECK(hipGetLastError());  // a refused launch surfaces here
   HIP_CHECK(hipMemcpyAsync(c->hctr, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->s));
   HIP_CHECK(hipStreamSynchronize(c->s));
 }
@@ -276,6 +279,15 @@ void build_bvh(hfcr_ctx *c, Pair &P, int i) {
   m.leaf_parent = ptr<int>(c->leaf_parent[i]);
   m.counters = ptr<int>(c->counters_n[i]);
   m.root_box = ptr<float>(c->root_box[i]);
+  // range (2 ints), top_pos, top_list, top_pre per node, and the top count
+  ensure(c->topo[i], ((size_t)5 * std::max(nt, 1) + 4) * sizeof(int));
+  int *tb = ptr<int>(c->topo[i]);
+  const size_t n1 = std::max(nt, 1);
+  m.range = reinterpret_cast<int2 *>(tb);
+  m.top_pos = tb + 2 * n1;
+  m.top_list = tb + 3 * n1;
+  m.top_pre = tb + 4 * n1;
+  m.top_count = tb + 5 * n1;
   if (nt == 0) return;
   launch_bounds(m, ptr<float>(c->scene_box[i]), c->s);
   ensure(c->sk0, (size_t)nt * sizeof(uint64_t));
@@ -289,8 +301,10 @@ void build_bvh(hfcr_ctx *c, Pair &P, int i) {
 
 void reset_counters(hfcr_ctx *c) { HIP_CHECK(hipMemsetAsync(c->ctr.p, 0, sizeof(Counters), c->s)); }
 
-// One detection pass in direction dir; leaves the sorted hits in hk/hv[dir].
-int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir) {
+// One detection pass in direction dir; leaves the hits in hk/hv[dir], sorted
+// when `sorted` (the order only matters for the returned round-0 list: the
+// stencils built from later rounds are sorted and made unique anyway).
+int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
   const int ei = dir == 0 ? 0 : 1, fi = dir == 0 ? 1 : 0;
   MeshDev &E = P.m[ei], &F = P.m[fi];
   if (P.dirty[fi]) {
@@ -316,7 +330,9 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir) {
     out.cand = &dc->cand;
     out.f32_unsure = &dc->f32_unsure;
     out.exact = &dc->exact;
+    out.visits = &dc->visits;
     out.overflow = &dc->overflow;
+    out.warm = 1;
     {
       Scope t(c, 2);
       launch_traverse(E, F, dir, P.tier0, P.hl, out, c->s);
@@ -326,11 +342,11 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir) {
       launch_exact(E, F, dir, P.hl, out, c->s);
     }
     readback(c);
-    if (c->hctr->overflow) throw StatusError{HFCR_E_DEVICE, "BVH traversal stack overflow"};
+    if (c->hctr->overflow & 1) throw StatusError{HFCR_E_DEVICE, "BVH traversal stack overflow"};
     const int64_t nh = c->hctr->hit_count[dir], na = c->hctr->amb_count[dir];
     if (nh <= P.hit_cap[dir] && na <= P.amb_cap[dir]) {
       Scope t(c, 4);
-      sort_inplace(c, out.keys, out.vals, nh, 1 + P.hl.bits_e + P.hl.bits_f);
+      if (sorted) sort_inplace(c, out.keys, out.vals, nh, 1 + P.hl.bits_e + P.hl.bits_f);
       P.hits_n[dir] = nh;
       return nh;
     }
@@ -410,8 +426,7 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
                                              std::to_string(HFCR_MAX_ZONE)};
   {
     Scope t(c, 6);
-    const int64_t k = info.maxk;
-    const int64_t stride = 2 * k * k + 5 * k + 8;  // doubles per slot: matrix, C, 3 vectors, 2 int arrays
+    const int64_t stride = (int64_t)solve_slot_doubles(info.maxk);
     const int64_t budget = (int64_t)1 << 28;       // doubles (2 GiB) across slots
     int nslots = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)info.nzones, 2048, budget / stride}));
     ensure(c->solve_scratch, (size_t)nslots * stride * sizeof(double));
@@ -429,6 +444,7 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
     a.slot_stride = stride;
     a.nslots = nslots;
     a.rank_def = &dc->rank_def;
+    a.pivoted = &dc->pivoted;
     a.tau = 1e-12;
     a.maxk = info.maxk;
     launch_solve(a, c->s);
@@ -620,7 +636,7 @@ void hfcr_destroy(hfcr_ctx *c) {
     if (b->p) (void)hipFree(b->p);
   for (int i = 0; i < 2; ++i) {
     DBuf *m[] = {&c->x64[i], &c->x32[i], &c->edges[i], &c->qedges[i], &c->leaf_tri[i], &c->nodes[i],
-                 &c->leaf_parent[i], &c->counters_n[i], &c->root_box[i], &c->codes[i], &c->scene_box[i],
+                 &c->leaf_parent[i], &c->counters_n[i], &c->root_box[i], &c->codes[i], &c->scene_box[i], &c->topo[i],
                  &c->hk[i], &c->hv[i], &c->amb[i]};
     for (DBuf *b : m)
       if (b->p) (void)hipFree(b->p);
@@ -653,6 +669,7 @@ hfcr_status hfcr_detect(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, int
       st->candidates = (int64_t)c->hctr->cand;
       st->exact_tests = (int64_t)c->hctr->exact;
       st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
+      st->node_visits = (int64_t)c->hctr->visits;
       st->converged = st->hits0 == 0;
       st->residual_hits = st->hits0;
     }
@@ -688,9 +705,9 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
         int64_t nhits = 0;
         if (alternate) {
           const int first = (int)(((int64_t)r + o.round_offset) & 1);
-          const int64_t nf = detect_dir(c, P, first);
+          const int64_t nf = detect_dir(c, P, first, r == 0);
           int64_t ns = 0;
-          if (r == 0 || nf == 0) ns = detect_dir(c, P, 1 - first);
+          if (r == 0 || nf == 0) ns = detect_dir(c, P, 1 - first, r == 0);
           else P.hits_n[1 - first] = 0;
           if (r == 0) write_hit_outputs(c, P, res, st, truncated);
           if (nf > 0) {
@@ -703,7 +720,7 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
         } else {
           for (int q = 0; q < P.ndirs; ++q) {
             const int dir = P.dirs[q];
-            const int64_t n = detect_dir(c, P, dir);
+            const int64_t n = detect_dir(c, P, dir, r == 0);
             if (n > 0) {
               act[nact++] = dir;
               nhits += n;
@@ -719,7 +736,7 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
         if (r == o.max_rounds) {
           residual = nhits;
           if (alternate && nact == 1 && P.hits_n[1 - act[0]] == 0 && act[0] == (int)(((int64_t)r + o.round_offset) & 1))
-            residual += detect_dir(c, P, 1 - act[0]);
+            residual += detect_dir(c, P, 1 - act[0], false);
           break;
         }
         const int64_t S = build_stencils(c, P, act, nact, c->st_keys);
@@ -749,6 +766,8 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
       st->exact_tests = (int64_t)c->hctr->exact;
       st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
       st->rank_deficient = c->hctr->rank_def;
+      st->node_visits = (int64_t)c->hctr->visits;
+      st->pivoted_zones = c->hctr->pivoted;
     }
     finish_timing(c, st);
     if (status != HFCR_OK) return status;

@@ -8,6 +8,8 @@
 // is rounded down and the upper bound up, so a box always contains the
 // exact triangle or segment (the closed-box overlap test never rejects a
 // true E-F intersection, whose crossing point lies in both boxes).
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -225,7 +227,8 @@ __device__ inline int prefix_len(const uint32_t *__restrict__ code, int n, int i
   return __clz(a ^ b);
 }
 
-__global__ void k_build_tree(const uint32_t *__restrict__ code, int n, BvhNode *nodes, int *leaf_parent) {
+__global__ void k_build_tree(const uint32_t *__restrict__ code, int n, BvhNode *nodes, int *leaf_parent,
+                             int2 *range) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1) return;
   // direction of the node's range: towards the neighbour sharing more bits
@@ -247,6 +250,7 @@ __global__ void k_build_tree(const uint32_t *__restrict__ code, int n, BvhNode *
   }
   int gamma = i + s * d + (d < 0 ? d : 0);
   int lo = i < j ? i : j, hi = i < j ? j : i;
+  range[i] = make_int2(lo, hi);
   int left = (lo == gamma) ? ~gamma : gamma;
   int right = (hi == gamma + 1) ? ~(gamma + 1) : gamma + 1;
   nodes[i].d.x = left;
@@ -267,8 +271,44 @@ __global__ void k_build_tree(const uint32_t *__restrict__ code, int n, BvhNode *
   }
 }
 
+// Refit chunks: each internal node covers a contiguous range of leaves (in
+// Morton order) and contains one end of its range in its own index, so the
+// nodes whose range lies inside chunk c have indices in that chunk.  Nodes
+// whose range crosses a chunk boundary ("top" nodes) are listed here.
+constexpr int kChunkBits = 10;
+constexpr int kChunk = 1 << kChunkBits;
+
+__global__ void k_mark_top(const int2 *__restrict__ range, const BvhNode *__restrict__ nodes, int n, int *top_pos,
+                           int *top_list, int *top_count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  int2 r = range[i];
+  if ((r.x >> kChunkBits) != (r.y >> kChunkBits)) {
+    int pos = atomicAdd(top_count, 1);
+    top_pos[i] = pos;
+    top_list[pos] = i;
+  } else {
+    top_pos[i] = -1;
+  }
+}
+
+__global__ void k_top_pre(const BvhNode *__restrict__ nodes, const int *__restrict__ top_pos,
+                          const int *__restrict__ top_list, const int *__restrict__ top_count, int *top_pre) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= *top_count) return;
+  int4 d = nodes[top_list[t]].d;
+  int pre = 0;
+  pre += (d.x < 0 || top_pos[d.x] < 0) ? 1 : 0;
+  pre += (d.y < 0 || top_pos[d.y] < 0) ? 1 : 0;
+  top_pre[t] = pre;
+}
+
 void launch_build_tree(const MeshDev &m, const uint32_t *codes, hipStream_t s) {
-  if (m.nt >= 2) k_build_tree<<<grid_for(m.nt - 1, 256), 256, 0, s>>>(codes, m.nt, m.nodes, m.leaf_parent);
+  if (m.nt < 2) return;
+  k_build_tree<<<grid_for(m.nt - 1, 256), 256, 0, s>>>(codes, m.nt, m.nodes, m.leaf_parent, m.range);
+  (void)hipMemsetAsync(m.top_count, 0, sizeof(int), s);
+  k_mark_top<<<grid_for(m.nt - 1, 256), 256, 0, s>>>(m.range, m.nodes, m.nt, m.top_pos, m.top_list, m.top_count);
+  k_top_pre<<<grid_for(m.nt - 1, 256), 256, 0, s>>>(m.nodes, m.top_pos, m.top_list, m.top_count, m.top_pre);
 }
 
 // -------------------------------------------------------------------- refit
@@ -347,8 +387,195 @@ __global__ void k_refit(const int4 *__restrict__ leaf_tri, int nt, const double 
   }
 }
 
+// Single-workgroup refit for trees whose arrival counters fit in LDS: every
+// climb stays on one CU, so workgroup-scope release/acquire on the LDS
+// counter orders the box stores and loads without any cache maintenance.
+constexpr int kRefitBlock = 1024;
+constexpr int kRefitWgMaxNodes = 38 * 1024;  // counters in LDS (152 KiB)
+// Measured slower than the multi-workgroup climb for 16k-leaf trees (one
+// workgroup walks 16 leaves per thread in sequence), so it is off.
+constexpr bool kRefitSingleWg = false;
+
+template <bool F32>
+__global__ __launch_bounds__(kRefitBlock) void k_refit_wg(const int4 *__restrict__ leaf_tri, int nt,
+                                                          const double *__restrict__ x64,
+                                                          const float *__restrict__ x32, int nv, BvhNode *nodes,
+                                                          const int *__restrict__ leaf_parent, float *root_box) {
+  extern __shared__ int cnt[];
+  for (int i = threadIdx.x; i < nt - 1; i += kRefitBlock) cnt[i] = 0;
+  __syncthreads();
+  for (int l = threadIdx.x; l < nt; l += kRefitBlock) {
+    const int4 t = leaf_tri[l];
+    float lo[3], hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (F32) {
+        float a = x32[(int64_t)k * nv + t.x], b = x32[(int64_t)k * nv + t.y], c = x32[(int64_t)k * nv + t.z];
+        lo[k] = fminf(a, fminf(b, c));
+        hi[k] = fmaxf(a, fmaxf(b, c));
+      } else {
+        double a = x64[(int64_t)k * nv + t.x], b = x64[(int64_t)k * nv + t.y], c = x64[(int64_t)k * nv + t.z];
+        lo[k] = __double2float_rd(fmin(a, fmin(b, c)));
+        hi[k] = __double2float_ru(fmax(a, fmax(b, c)));
+      }
+    }
+    const int pp = leaf_parent[l];
+    int node = pp >> 1;
+    store_child_box(&nodes[node], pp & 1, lo, hi);
+    while (true) {
+      // release our box store, acquire the sibling's (workgroup scope)
+      const int old = __hip_atomic_fetch_add(&cnt[node], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;
+      const BvhNode nd = nodes[node];
+      lo[0] = fminf(nd.a.x, nd.b.z); lo[1] = fminf(nd.a.y, nd.b.w); lo[2] = fminf(nd.a.z, nd.c.x);
+      hi[0] = fmaxf(nd.a.w, nd.c.y); hi[1] = fmaxf(nd.b.x, nd.c.z); hi[2] = fmaxf(nd.b.y, nd.c.w);
+      const int parent = nd.d.z;
+      if (parent < 0) {
+        for (int k = 0; k < 3; ++k) {
+          root_box[k] = lo[k];
+          root_box[3 + k] = hi[k];
+        }
+        break;
+      }
+      store_child_box(&nodes[parent], nd.d.w, lo, hi);
+      node = parent;
+    }
+  }
+}
+
+// Two-phase refit.  Phase 1: one workgroup per chunk of kChunk leaves climbs
+// through the nodes inside its chunk, with arrival counters in LDS and
+// workgroup-scope release/acquire, stopping below the first top node.
+// Phase 2: one workgroup climbs the top nodes, whose counters start at the
+// number of children phase 1 already finished.  No step needs device-wide
+// cache maintenance; the kernel boundary orders the two phases.
+__device__ inline void leaf_box(const int4 t, bool f32, const double *__restrict__ x64, const float *__restrict__ x32,
+                                int nv, float lo[3], float hi[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (f32) {
+      float a = x32[(int64_t)k * nv + t.x], b = x32[(int64_t)k * nv + t.y], c = x32[(int64_t)k * nv + t.z];
+      lo[k] = fminf(a, fminf(b, c));
+      hi[k] = fmaxf(a, fmaxf(b, c));
+    } else {
+      double a = x64[(int64_t)k * nv + t.x], b = x64[(int64_t)k * nv + t.y], c = x64[(int64_t)k * nv + t.z];
+      lo[k] = __double2float_rd(fmin(a, fmin(b, c)));
+      hi[k] = __double2float_ru(fmax(a, fmax(b, c)));
+    }
+  }
+}
+
+__device__ inline void node_union(const BvhNode &nd, float lo[3], float hi[3]) {
+  lo[0] = fminf(nd.a.x, nd.b.z); lo[1] = fminf(nd.a.y, nd.b.w); lo[2] = fminf(nd.a.z, nd.c.x);
+  hi[0] = fmaxf(nd.a.w, nd.c.y); hi[1] = fmaxf(nd.b.x, nd.c.z); hi[2] = fmaxf(nd.b.y, nd.c.w);
+}
+
+template <bool F32>
+__global__ __launch_bounds__(kChunk) void k_refit_chunk(const int4 *__restrict__ leaf_tri, int nt,
+                                                        const double *__restrict__ x64, const float *__restrict__ x32,
+                                                        int nv, BvhNode *nodes, const int *__restrict__ leaf_parent,
+                                                        const int *__restrict__ top_pos, float *root_box) {
+  __shared__ int cnt[kChunk];
+  const int base = blockIdx.x * kChunk;
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int l = base + threadIdx.x;
+  if (l >= nt) return;
+  float lo[3], hi[3];
+  leaf_box(leaf_tri[l], F32, x64, x32, nv, lo, hi);
+  const int pp = leaf_parent[l];
+  int node = pp >> 1;
+  store_child_box(&nodes[node], pp & 1, lo, hi);
+  while (top_pos[node] < 0) {
+    const int old = __hip_atomic_fetch_add(&cnt[node - base], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (old == 0) return;
+    const BvhNode nd = nodes[node];
+    node_union(nd, lo, hi);
+    const int parent = nd.d.z;
+    if (parent < 0) {
+      for (int k = 0; k < 3; ++k) {
+        root_box[k] = lo[k];
+        root_box[3 + k] = hi[k];
+      }
+      return;
+    }
+    store_child_box(&nodes[parent], nd.d.w, lo, hi);
+    node = parent;
+  }
+}
+
+constexpr int kTopLds = 32 * 1024;  // top nodes handled by the two-phase refit
+
+__global__ __launch_bounds__(1024) void k_refit_top(BvhNode *nodes, const int *__restrict__ top_pos,
+                                                    const int *__restrict__ top_list, const int *__restrict__ top_pre,
+                                                    const int *__restrict__ top_count, float *root_box) {
+  extern __shared__ int tcnt[];
+  const int ntop = *top_count;
+  for (int t = threadIdx.x; t < ntop; t += 1024) tcnt[t] = top_pre[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntop; t += 1024) {
+    if (top_pre[t] != 2) continue;  // a climb starts where both children are done
+    int node = top_list[t];
+    while (true) {
+      float lo[3], hi[3];
+      const BvhNode nd = nodes[node];
+      node_union(nd, lo, hi);
+      const int parent = nd.d.z;
+      if (parent < 0) {
+        for (int k = 0; k < 3; ++k) {
+          root_box[k] = lo[k];
+          root_box[3 + k] = hi[k];
+        }
+        break;
+      }
+      store_child_box(&nodes[parent], nd.d.w, lo, hi);
+      const int old =
+          __hip_atomic_fetch_add(&tcnt[top_pos[parent]], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old != 1) break;  // the other child is not finished yet
+      node = parent;
+    }
+  }
+}
+
 void launch_refit(const MeshDev &m, hipStream_t s) {
   if (m.nt <= 0) return;
+  const int nchunks = (m.nt + kChunk - 1) / kChunk;
+  if (m.nt >= 2 && (int64_t)nchunks * 64 <= kTopLds) {
+    if (m.f32)
+      k_refit_chunk<true><<<nchunks, kChunk, 0, s>>>(m.leaf_tri, m.nt, m.x64, m.x32, m.nv, m.nodes, m.leaf_parent,
+                                                     m.top_pos, m.root_box);
+    else
+      k_refit_chunk<false><<<nchunks, kChunk, 0, s>>>(m.leaf_tri, m.nt, m.x64, m.x32, m.nv, m.nodes,
+                                                      m.leaf_parent, m.top_pos, m.root_box);
+    if (nchunks > 1) {
+      static bool attr_set = false;
+      if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refit_top),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kTopLds * (int)sizeof(int));
+        attr_set = true;
+      }
+      const size_t bytes = (size_t)std::min<int64_t>((int64_t)nchunks * 64, m.nt) * sizeof(int);
+      k_refit_top<<<1, 1024, bytes, s>>>(m.nodes, m.top_pos, m.top_list, m.top_pre, m.top_count, m.root_box);
+    }
+    return;
+  }
+  if (kRefitSingleWg && m.nt >= 2 && m.nt - 1 <= kRefitWgMaxNodes) {
+    static bool attr_set[2] = {false, false};
+    const size_t bytes = (size_t)(m.nt - 1) * sizeof(int);
+    const void *fn = m.f32 ? reinterpret_cast<const void *>(&k_refit_wg<true>)
+                           : reinterpret_cast<const void *>(&k_refit_wg<false>);
+    if (!attr_set[m.f32 ? 1 : 0]) {
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kRefitWgMaxNodes * (int)sizeof(int));
+      attr_set[m.f32 ? 1 : 0] = true;
+    }
+    if (m.f32)
+      k_refit_wg<true><<<1, kRefitBlock, bytes, s>>>(m.leaf_tri, m.nt, m.x64, m.x32, m.nv, m.nodes, m.leaf_parent,
+                                                     m.root_box);
+    else
+      k_refit_wg<false><<<1, kRefitBlock, bytes, s>>>(m.leaf_tri, m.nt, m.x64, m.x32, m.nv, m.nodes,
+                                                      m.leaf_parent, m.root_box);
+    return;
+  }
   if (m.f32)
     k_refit<true><<<grid_for(m.nt, 256), 256, 0, s>>>(m.leaf_tri, m.nt, m.x64, m.x32, m.nv, m.nodes,
                                                       m.leaf_parent, m.counters, m.root_box);

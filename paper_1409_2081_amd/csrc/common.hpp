@@ -36,6 +36,11 @@ struct MeshDev {
   int *leaf_parent = nullptr;// [nt] parent node of each leaf (slot in bit 31)
   int *counters = nullptr;   // [nt] refit visit counters (self-clearing)
   float *root_box = nullptr; // [6]
+  int2 *range = nullptr;     // [nt] leaf range (lo, hi) of each internal node
+  int *top_pos = nullptr;    // [nt] position in top_list, or -1
+  int *top_list = nullptr;   // [nt] internal nodes whose range crosses a refit chunk
+  int *top_pre = nullptr;    // [nt] per top node: children finished by the chunk pass
+  int *top_count = nullptr;  // [1]
   const double *inv_mass = nullptr;
   bool small_coords = true;  // every |coordinate| <= 2^32 (float32 filter valid)
 };

@@ -36,7 +36,9 @@ struct DcdOut {
   unsigned long long *cand;     // narrow-phase tests
   unsigned long long *f32_unsure;
   unsigned long long *exact;    // exact-tier tests
+  unsigned long long *visits;   // BVH nodes fetched
   int *overflow;         // traversal stack overflow flag
+  int warm;              // warm the L2 before traversing
 };
 void launch_traverse(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, bool tier0, HitLayout lay,
                      const DcdOut &out, hipStream_t s);
@@ -79,14 +81,16 @@ struct SolveArgs {
   const double *w_a, *w_b;  // inverse masses or null
   int nv_a;
   double *lambda;           // [S]
-  double *scratch;          // per-slot 2*maxk^2 doubles
+  double *scratch;          // per-slot solve_slot_doubles(maxk) doubles
   int64_t slot_stride;      // doubles per slot
   int nslots;
   int *rank_def;            // count of rank-deficient zones
+  int *pivoted;             // zones that needed the pivoted (rank-revealing) path
   double tau;
   int maxk;                 // largest zone
 };
 void launch_solve(const SolveArgs &a, hipStream_t s);
+size_t solve_slot_doubles(int maxk);  // scratch doubles per workgroup slot
 void launch_incidence(const Constraint *con, int64_t S, int bits_s, uint64_t *keys, hipStream_t s);
 void launch_update(const uint64_t *keys, int64_t n, int bits_s, const Constraint *con, const double *lambda,
                    MeshDev &A, MeshDev &B, hipStream_t s);

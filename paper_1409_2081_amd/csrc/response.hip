@@ -18,7 +18,7 @@
 // Zone solve (Eq. 7, Eq. 8): A lambda = r with A_ij = (n_i . n_j) *
 // sum over shared vertices v of w_v c_iv c_jv.  One workgroup per zone
 // factors A by Cholesky with diagonal pivoting, stopping when the largest
-// remaining pivot falls below tau * max(diag A) (tau = 1e-12).  Full rank:
+// remaining pivot is at most tau * max(diag A) (tau = 1e-12).  Full rank:
 // two triangular solves.  Rank r < k: with the k-by-r factor L,
 // lambda = L (L^T L)^-1 (L^T L)^-1 L^T r, the minimum-norm least-squares
 // solution, for which x' below does not depend on the choice of lambda.
@@ -233,16 +233,23 @@ void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, u
 }
 
 // -------------------------------------------------------------- zone solve
-// Storage: the lower triangle of the zone matrix, S[i*k + l] for i >= l
-// (index order).  Pivot step j chooses p = argmax of the remaining diagonal
-// (ties: smaller index), stores L(i, j) = A_ip / sqrt(A_pp) where A_ip was
-// kept (S[max(i,p)*k + min(i,p)]) and updates the remaining lower triangle.
-// The remaining indices are kept in increasing order by a stable compaction,
-// so "lower" keeps its meaning in index order at every step.
-constexpr int kSmallZone = 64;     // zones up to this size: one wave, matrix in LDS
-constexpr int kLdsCon = 512;       // zones up to this size keep constraints in LDS
-constexpr int kBigBlock = 256;
-constexpr int kMaxZoneLds = 4096;  // == HFCR_MAX_ZONE
+// Storage: the packed lower triangle of the zone matrix, S[i(i+1)/2 + l] for
+// i >= l (index order).  Pivot step j takes p = argmax of the remaining
+// diagonal (ties: smaller index), stores L(i, j) = A_ip / sqrt(A_pp) where
+// A_ip was kept, and updates the remaining lower triangle; the next step's
+// argmax and the forward substitution L~ y = r~ are folded into that update,
+// so a factorization step costs two barriers and the forward solve none.
+// The remaining indices stay in increasing order (stable compaction), so
+// "lower" keeps its meaning at every step.
+//
+// Zones of up to kZoneLds stencils keep the matrix and every vector in LDS
+// (sized at launch for the largest such zone); larger zones keep the matrix
+// in the workgroup's global slot (L2-resident) and the rest in LDS when it
+// fits, else in the slot too.
+constexpr int kSolveBlock = 256;
+constexpr int kZoneLds = 176;
+constexpr int kZoneVecLds = 1024;
+constexpr int kZoneMax = 4096;  // == HFCR_MAX_ZONE
 
 __device__ inline double inv_mass(int v, const double *wa, const double *wb, int nva) {
   if (v < nva) return wa ? wa[v] : 1.0;
@@ -251,16 +258,15 @@ __device__ inline double inv_mass(int v, const double *wa, const double *wb, int
 
 __device__ inline double coef(int slot) { return slot == 0 ? 1.0 : -1.0 / 3.0; }
 
-__device__ inline int64_t lidx(int i, int l, int k) {
-  return i >= l ? (int64_t)i * k + l : (int64_t)l * k + i;
-}
+__device__ inline int64_t tri_base(int i) { return (int64_t)i * (i + 1) / 2; }
+__device__ inline int64_t lp(int i, int l) { return i >= l ? tri_base(i) + l : tri_base(l) + i; }
 
-// (value, position) pair reduction over a wavefront; ties -> smaller key
+// (value, position, key) reduction over a wavefront: larger value, ties -> smaller key
 __device__ inline void wave_argmax(double &v, int &pos, int &key) {
   for (int off = 32; off > 0; off >>= 1) {
-    double v2 = __shfl_xor(v, off);
-    int p2 = __shfl_xor(pos, off);
-    int k2 = __shfl_xor(key, off);
+    const double v2 = __shfl_xor(v, off);
+    const int p2 = __shfl_xor(pos, off);
+    const int k2 = __shfl_xor(key, off);
     if (v2 > v || (v2 == v && k2 >= 0 && (key < 0 || k2 < key))) {
       v = v2;
       pos = p2;
@@ -269,109 +275,327 @@ __device__ inline void wave_argmax(double &v, int &pos, int &key) {
   }
 }
 
-template <int BLOCK>
-struct SolveShared {
-  static constexpr int kCon = BLOCK == 64 ? kSmallZone : kLdsCon;
-  Constraint con[kCon];
-  double wv[BLOCK / 64];
-  int wp[BLOCK / 64], wk[BLOCK / 64];
-  int rem[2][BLOCK == 64 ? kSmallZone : kMaxZoneLds];
-  double lcol[BLOCK == 64 ? kSmallZone : kMaxZoneLds];
-  double s_y;
-  double mat[BLOCK == 64 ? kSmallZone * kSmallZone : 1];
-};
+// Per-zone arrays: 7 doubles (n.xyz, r, rhs, lcol, lam) and 8 ints
+// (vertex ids x4, piv, step_of, rem x2) per stencil, plus y and 1/L_jj.
+constexpr int kVecDoubles = 9;
+constexpr int kVecInts = 8;
 
-// Zones with kmin < k <= kmax; the matrix lives in LDS when BLOCK == 64.
+__host__ __device__ inline int round8(int k) { return (k + 7) / 8 * 8; }
+__host__ __device__ inline size_t zone_vec_bytes(int k) {
+  return (size_t)round8(k) * (kVecDoubles * 8 + kVecInts * 4);
+}
+// matrix doubles: the larger of the 8x8-tiled lower triangle and the packed one
+__host__ __device__ inline size_t zone_mat_doubles(int k) {
+  const size_t t = (size_t)(k + 7) / 8;
+  const size_t tiled = t * (t + 1) / 2 * 64, packed = (size_t)k * (k + 1) / 2;
+  return tiled > packed ? tiled : packed;
+}
+__host__ __device__ inline size_t zone_lds_bytes(bool mat_lds, int kcap) {
+  return (mat_lds ? zone_mat_doubles(kcap) * 8 : 0) + zone_vec_bytes(kcap) + 4 * 16 + 64;
+}
+
+// ---- tiled unpivoted Cholesky (fast path) --------------------------------
+// Lower tiles of 8 x 8, tile (I, J) for I >= J at (I(I+1)/2 + J) * 64,
+// row-major inside the tile.  The matrix is padded to a multiple of 8 with
+// diag = max diag A (so padded rows never trip the pivot test) and rhs 0.
+constexpr int TB = 8;
+__device__ inline int64_t tile_off(int I, int J) { return ((int64_t)I * (I + 1) / 2 + J) * (TB * TB); }
+
+// Returns true when every pivot exceeds thr_u; on success lam[0..k) holds the
+// solution.  On failure the matrix storage is garbage (the caller reassembles).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a, int kmin, int kmax) {
-  __shared__ SolveShared<BLOCK> sh;
-  constexpr bool kLds = BLOCK == 64;
-  constexpr int TY = BLOCK == 64 ? 8 : 16;  // 2-D thread tiling for the trailing update
+__device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny, const double *nz,
+                            const int *v0, const int *v1, const int *v2, const int *v3, const double *rr,
+                            double *rhs, double *y, double *dinv, double *lam, const SolveArgs &a, double dmax,
+                            int *flag) {
+  const int tid = threadIdx.x;
+  const int T = (k + TB - 1) / TB;
+  const int kp = T * TB;
+  // assemble the lower tiles (diagonal tiles: full, the upper half is ignored)
+  const int64_t ntile_el = (int64_t)T * (T + 1) / 2 * (TB * TB);
+  for (int64_t e = tid; e < ntile_el; e += BLOCK) {
+    const int64_t t = e >> 6;
+    const int rc = (int)(e & 63), r = rc >> 3, c = rc & 7;
+    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((int64_t)I * (I + 1) / 2 > t) --I;
+    while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = (int)(t - (int64_t)I * (I + 1) / 2);
+    const int i = I * TB + r, l = J * TB + c;
+    double val = 0.0;
+    if (i < k && l < k) {
+      const int vi[4] = {v0[i], v1[i], v2[i], v3[i]};
+      const int vl[4] = {v0[l], v1[l], v2[l], v3[l]};
+      double acc = 0.0;
+      for (int s = 0; s < 4; ++s)
+        for (int u = 0; u < 4; ++u)
+          if (vi[s] == vl[u]) acc += inv_mass(vi[s], a.w_a, a.w_b, a.nv_a) * coef(s) * coef(u);
+      val = acc * (nx[i] * nx[l] + ny[i] * ny[l] + nz[i] * nz[l]);
+    } else if (i == l) {
+      val = dmax > 0.0 ? dmax : 1.0;
+    }
+    M[e] = val;
+  }
+  for (int i = tid; i < kp; i += BLOCK) rhs[i] = i < k ? rr[i] : 0.0;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  const double thr_u = 1e-6 * dmax;
+  for (int J = 0; J < T; ++J) {
+    double *D = M + tile_off(J, J);
+    // (1) diagonal tile and the forward substitution of its block, in registers
+    if (tid == 0) {
+      double t[TB][TB], rb[TB], di[TB];
+#pragma unroll
+      for (int r = 0; r < TB; ++r) {
+        rb[r] = rhs[J * TB + r];
+#pragma unroll
+        for (int c = 0; c <= r; ++c) t[r][c] = D[r * TB + c];
+      }
+      bool bad = false;
+#pragma unroll
+      for (int c = 0; c < TB; ++c) {
+        const double piv = t[c][c];
+        bad = bad || !(piv > thr_u);
+        const double l = sqrt(fmax(piv, 0.0)), inv = 1.0 / l;
+        t[c][c] = l;
+        di[c] = inv;
+#pragma unroll
+        for (int r = c + 1; r < TB; ++r) t[r][c] = t[r][c] * inv;
+#pragma unroll
+        for (int r = c + 1; r < TB; ++r)
+#pragma unroll
+          for (int r2 = c + 1; r2 <= r; ++r2) t[r][r2] = t[r][r2] - t[r][c] * t[r2][c];
+      }
+      if (bad) {
+        *flag = 1;
+      } else {
+#pragma unroll
+        for (int c = 0; c < TB; ++c) {
+          const double yc = rb[c] * di[c];
+          y[J * TB + c] = yc;
+#pragma unroll
+          for (int r = c + 1; r < TB; ++r) rb[r] = rb[r] - t[r][c] * yc;
+        }
+#pragma unroll
+        for (int r = 0; r < TB; ++r) {
+          dinv[J * TB + r] = di[r];
+#pragma unroll
+          for (int c = 0; c <= r; ++c) D[r * TB + c] = t[r][c];
+        }
+      }
+    }
+    __syncthreads();
+    if (*flag) return false;
+    // (2) panel: L_IJ = A_IJ L_JJ^-T, and the forward-substitution update
+    for (int it = tid; it < (T - J - 1) * TB; it += BLOCK) {
+      const int I = J + 1 + it / TB, r = it % TB;
+      double *B = M + tile_off(I, J) + r * TB;
+      double x[TB];
+#pragma unroll
+      for (int c = 0; c < TB; ++c) x[c] = B[c];
+#pragma unroll
+      for (int c = 0; c < TB; ++c) {
+        double s = x[c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) s = s - x[m] * D[c * TB + m];
+        x[c] = s * dinv[J * TB + c];
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < TB; ++c) {
+        B[c] = x[c];
+        acc = acc + x[c] * y[J * TB + c];
+      }
+      rhs[I * TB + r] = rhs[I * TB + r] - acc;
+    }
+    __syncthreads();
+    // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I, one tile row per item
+    const int nrem = T - J - 1;
+    const int64_t items = (int64_t)nrem * (nrem + 1) / 2 * TB;
+    for (int64_t it = tid; it < items; it += BLOCK) {
+      const int64_t p = it >> 3;
+      const int r = (int)(it & 7);
+      int u = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+      while ((int64_t)u * (u + 1) / 2 > p) --u;
+      while ((int64_t)(u + 1) * (u + 2) / 2 <= p) ++u;
+      const int v = (int)(p - (int64_t)u * (u + 1) / 2);
+      const int I = J + 1 + u, K = J + 1 + v;
+      const double *LI = M + tile_off(I, J) + r * TB;
+      const double *LK = M + tile_off(K, J);
+      double li[TB];
+#pragma unroll
+      for (int m = 0; m < TB; ++m) li[m] = LI[m];
+      double *C = M + tile_off(I, K) + r * TB;
+      double out[TB];
+#pragma unroll
+      for (int c = 0; c < TB; ++c) out[c] = C[c];
+#pragma unroll
+      for (int c = 0; c < TB; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < TB; ++m) s = s + li[m] * LK[c * TB + m];
+        out[c] = out[c] - s;
+      }
+#pragma unroll
+      for (int c = 0; c < TB; ++c) C[c] = out[c];
+    }
+    __syncthreads();
+  }
+  // backward: L^T lambda = y, tile by tile
+  for (int J = T - 1; J >= 0; --J) {
+    const double *D = M + tile_off(J, J);
+    if (tid == 0) {
+      double t[TB][TB], yb[TB], lb[TB];
+#pragma unroll
+      for (int r = 0; r < TB; ++r) {
+        yb[r] = y[J * TB + r];
+#pragma unroll
+        for (int c = 0; c <= r; ++c) t[r][c] = D[r * TB + c];
+      }
+#pragma unroll
+      for (int c = TB - 1; c >= 0; --c) {
+        double s2 = yb[c];
+#pragma unroll
+        for (int m = c + 1; m < TB; ++m) s2 = s2 - t[m][c] * lb[m];
+        lb[c] = s2 * dinv[J * TB + c];
+      }
+#pragma unroll
+      for (int c = 0; c < TB; ++c) lam[J * TB + c] = lb[c];
+    }
+    __syncthreads();
+    for (int it = tid; it < J * TB; it += BLOCK) {
+      const int K = it / TB, c = it % TB;
+      const double *B = M + tile_off(J, K);
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < TB; ++r) s = s + B[r * TB + c] * lam[J * TB + r];
+      y[K * TB + c] = y[K * TB + c] - s;
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+template <bool MAT_LDS, bool VEC_LDS>
+__global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, int kcap) {
+  constexpr bool vec_lds = VEC_LDS;  // compile-time, so LDS accesses stay ds_* (never flat)
+  extern __shared__ double dyn[];
+  constexpr int TY = 16;  // 16 x 16 tiling of the trailing update
+  constexpr int NW = kSolveBlock / 64;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int tx = tid % TY, ty = tid / TY;
+  double *S_lds = dyn;
+  double *vec_lds_base = dyn + (MAT_LDS ? (int64_t)zone_mat_doubles(kcap) : 0);
+  double *wv = vec_lds_base + (vec_lds ? zone_vec_bytes(kcap) / 8 : 0);
+  int *wp = reinterpret_cast<int *>(wv + NW);
+  int *wk = wp + NW;
+  int *flag = wk + NW;
   for (int z = blockIdx.x; z < a.nzones; z += gridDim.x) {
     const int st = (int)a.starts[z];
     const int k = (int)a.starts[z + 1] - st;
-    if (k <= kmin || k > kmax) continue;
+    if (k <= kmin || k > kcap) continue;
     double *slot = a.scratch + (int64_t)blockIdx.x * a.slot_stride;
-    double *S = kLds ? sh.mat : slot;
-    double *Cm = slot + (int64_t)k * k;
-    double *vec = slot + 2 * (int64_t)k * k;  // rhs, y, lam: 3k doubles
-    double *rhs = vec, *y = vec + k, *lam = vec + 2 * k;
-    int *piv = reinterpret_cast<int *>(vec + 3 * k);  // k
-    int *step_of = piv + k;                           // k
-    const bool con_lds = k <= SolveShared<BLOCK>::kCon;
-    for (int i = tid; i < k && con_lds; i += BLOCK) sh.con[i] = a.con[a.order[st + i]];
+    double *S = MAT_LDS ? S_lds : slot;
+    double *Cm = slot + zone_mat_doubles(k);  // rank-deficient case only (packed r x r)
+    double *vb = vec_lds ? vec_lds_base : Cm + tri_base(k);
+    const int k8 = round8(k);
+    double *nx = vb, *ny = vb + k8, *nz = vb + 2 * k8, *rr = vb + 3 * k8, *rhs = vb + 4 * k8, *lcol = vb + 5 * k8,
+           *lam = vb + 6 * k8, *y = vb + 7 * k8, *dinv = vb + 8 * k8;
+    int *ib = reinterpret_cast<int *>(vb + kVecDoubles * k8);
+    int *v0 = ib, *v1 = ib + k8, *v2 = ib + 2 * k8, *v3 = ib + 3 * k8, *piv = ib + 4 * k8, *step_of = ib + 5 * k8,
+        *rem0 = ib + 6 * k8, *rem1 = ib + 7 * k8;
+    // stage the zone's constraints
+    for (int i = tid; i < k; i += kSolveBlock) {
+      const Constraint c = a.con[a.order[st + i]];
+      nx[i] = c.n.x;
+      ny[i] = c.n.y;
+      nz[i] = c.n.z;
+      rr[i] = c.n.w;
+      rhs[i] = c.n.w;
+      v0[i] = c.v.x;
+      v1[i] = c.v.y;
+      v2[i] = c.v.z;
+      v3[i] = c.v.w;
+      step_of[i] = k;
+      rem0[i] = i;
+    }
     __syncthreads();
-#define CON(i) (con_lds ? sh.con[(i)] : a.con[a.order[st + (i)]])
-    // assemble the lower triangle of A
-    for (int i = ty; i < k; i += BLOCK / TY) {
-      const Constraint ci = CON(i);
-      const int vi[4] = {ci.v.x, ci.v.y, ci.v.z, ci.v.w};
+    // largest diagonal entry: A_ii = (n_i . n_i) (w_x0 + (w_1 + w_2 + w_3) / 9)
+    double dmax = 0.0;
+    {
+      double v = 0.0;
+      int pos = 0, key = 0;
+      for (int i = tid; i < k; i += kSolveBlock) {
+        const double d = (nx[i] * nx[i] + ny[i] * ny[i] + nz[i] * nz[i]) *
+                         (inv_mass(v0[i], a.w_a, a.w_b, a.nv_a) +
+                          (inv_mass(v1[i], a.w_a, a.w_b, a.nv_a) + inv_mass(v2[i], a.w_a, a.w_b, a.nv_a) +
+                           inv_mass(v3[i], a.w_a, a.w_b, a.nv_a)) / 9.0);
+        v = fmax(v, d);
+      }
+      wave_argmax(v, pos, key);
+      if (lane == 0) wv[wave] = v;
+      __syncthreads();
+      for (int w = 0; w < NW; ++w) dmax = fmax(dmax, wv[w]);
+      __syncthreads();
+    }
+    if (tiled_solve<kSolveBlock>(S, k, nx, ny, nz, v0, v1, v2, v3, rr, rhs, y, dinv, lam, a, dmax, flag)) {
+      for (int i = tid; i < k; i += kSolveBlock) a.lambda[a.order[st + i]] = lam[i];
+      __syncthreads();
+      continue;
+    }
+    // fallback: Cholesky with diagonal pivoting (rank-revealing)
+    if (tid == 0) atomicAdd(a.pivoted, 1);
+    for (int i = tid; i < k; i += kSolveBlock) {
+      rhs[i] = rr[i];
+      step_of[i] = k;
+      rem0[i] = i;
+    }
+    __syncthreads();
+    // assemble the packed lower triangle
+    for (int i = ty; i < k; i += kSolveBlock / TY) {
+      const int vi[4] = {v0[i], v1[i], v2[i], v3[i]};
       double wi[4];
       for (int s = 0; s < 4; ++s) wi[s] = inv_mass(vi[s], a.w_a, a.w_b, a.nv_a) * coef(s);
+      const double nix = nx[i], niy = ny[i], niz = nz[i];
+      const int64_t base = tri_base(i);
       for (int l = tx; l <= i; l += TY) {
-        const Constraint cl = CON(l);
-        const int vl[4] = {cl.v.x, cl.v.y, cl.v.z, cl.v.w};
+        const int vl[4] = {v0[l], v1[l], v2[l], v3[l]};
         double acc = 0.0;
         for (int s = 0; s < 4; ++s)
           for (int t = 0; t < 4; ++t)
             if (vi[s] == vl[t]) acc += wi[s] * coef(t);
-        S[(int64_t)i * k + l] = acc * (ci.n.x * cl.n.x + ci.n.y * cl.n.y + ci.n.z * cl.n.z);
+        S[base + l] = acc * (nix * nx[l] + niy * ny[l] + niz * nz[l]);
       }
     }
-    for (int i = tid; i < k; i += BLOCK) {
-      rhs[i] = CON(i).n.w;
-      step_of[i] = k;
-      sh.rem[0][i] = i;
-    }
     __syncthreads();
-    // largest diagonal entry (the pivot threshold is relative to it)
-    double dmax = 0.0;
+    // first argmax (also the largest diagonal, which scales the threshold)
     {
       double v = -1.0;
       int pos = -1, key = -1;
-      for (int i = tid; i < k; i += BLOCK) {
-        const double d = S[(int64_t)i * k + i];
+      for (int i = tid; i < k; i += kSolveBlock) {
+        const double d = S[tri_base(i) + i];
         if (d > v) { v = d; pos = i; key = i; }
       }
       wave_argmax(v, pos, key);
-      if (lane == 0) sh.wv[wave] = v;
-      __syncthreads();
-      for (int w = 0; w < BLOCK / 64; ++w) dmax = fmax(dmax, sh.wv[w]);
+      if (lane == 0) { wv[wave] = v; wp[wave] = pos; wk[wave] = key; }
       __syncthreads();
     }
+    dmax = wv[0];
+    for (int w = 1; w < NW; ++w) dmax = fmax(dmax, wv[w]);
     const double thresh = a.tau * dmax;
-    int rank = k, cur = 0;
+    int rank = k;
+    int *rem = rem0, *rem2 = rem1;
     for (int j = 0; j < k; ++j) {
       const int nrem = k - j;
-      const int *rem = sh.rem[cur];
-      int *rem2 = sh.rem[cur ^ 1];
-      // A: argmax of the remaining diagonal
-      double v = -1.0;
-      int pos = -1, key = -1;
-      for (int q = tid; q < nrem; q += BLOCK) {
-        const int i = rem[q];
-        const double d = S[(int64_t)i * k + i];
-        if (d > v || (d == v && i < key)) { v = d; pos = q; key = i; }
-      }
-      wave_argmax(v, pos, key);
-      if (lane == 0) {
-        sh.wv[wave] = v;
-        sh.wp[wave] = pos;
-        sh.wk[wave] = key;
-      }
-      __syncthreads();
-      double best = sh.wv[0];
-      int q0 = sh.wp[0], p = sh.wk[0];
-      for (int w = 1; w < BLOCK / 64; ++w) {
-        const double v2 = sh.wv[w];
-        const int k2 = sh.wk[w];
-        if (v2 > best || (v2 == best && k2 >= 0 && (p < 0 || k2 < p))) {
-          best = v2;
-          q0 = sh.wp[w];
-          p = k2;
+      double best = wv[0];
+      int q0 = wp[0], p = wk[0];
+      for (int w = 1; w < NW; ++w) {
+        const double vw = wv[w];
+        const int kw = wk[w];
+        if (vw > best || (vw == best && kw >= 0 && (p < 0 || kw < p))) {
+          best = vw;
+          q0 = wp[w];
+          p = kw;
         }
       }
       if (!(best > thresh)) {
@@ -379,103 +603,186 @@ __global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a, int kmin, int kmax
         break;
       }
       const double lpp = sqrt(best);
-      // B: column p of L, and the stable compaction of the remaining list
-      for (int q = tid; q < nrem; q += BLOCK) {
+      const double inv = 1.0 / lpp;
+      const double yj = rhs[p] * inv;  // forward substitution, step j
+      // B: column p of L and the stable compaction of the remaining list
+      for (int q = tid; q < nrem; q += kSolveBlock) {
         if (q == q0) continue;
         const int i = rem[q];
-        const int64_t at = lidx(i, p, k);
-        const double l = S[at] / lpp;
+        const int64_t at = lp(i, p);
+        const double l = S[at] * inv;
         S[at] = l;
         const int qn = q < q0 ? q : q - 1;
         rem2[qn] = i;
-        sh.lcol[qn] = l;
+        lcol[qn] = l;
       }
       if (tid == 0) {
-        S[(int64_t)p * k + p] = lpp;
+        S[tri_base(p) + p] = lpp;
+        dinv[j] = inv;
+        y[j] = yj;
         piv[j] = p;
         step_of[p] = j;
       }
       __syncthreads();
-      // C: trailing update of the remaining lower triangle
+      // C: trailing update, forward-substitution update, next argmax
       const int nr = nrem - 1;
-      for (int r = ty; r < nr; r += BLOCK / TY) {
-        const int i = rem2[r];
-        const double li = sh.lcol[r];
-        double *row = S + (int64_t)i * k;
-        for (int c = tx; c <= r; c += TY) row[rem2[c]] = row[rem2[c]] - li * sh.lcol[c];
+      double v = -1.0;
+      int pos = -1, key = -1;
+      if (MAT_LDS) {
+        // this thread's columns c = tx + 16 m and rows r = ty + 16 a, held in
+        // registers; each row's entries are loaded before any is stored (the
+        // columns of a row are distinct, so the stores cannot alias the loads)
+        constexpr int MC = (kZoneLds + TY - 1) / TY;
+        int cidx[MC];
+        double cval[MC];
+#pragma unroll
+        for (int m = 0; m < MC; ++m) {
+          const int c = tx + TY * m;
+          cidx[m] = c < nr ? rem2[c] : 0;
+          cval[m] = c < nr ? lcol[c] : 0.0;
+        }
+        int ridx[MC];
+        double rval[MC];
+#pragma unroll
+        for (int a2 = 0; a2 < MC; ++a2) {
+          const int r = ty + TY * a2;
+          ridx[a2] = r < nr ? rem2[r] : 0;
+          rval[a2] = r < nr ? lcol[r] : 0.0;
+        }
+#pragma unroll
+        for (int a2 = 0; a2 < MC; ++a2) {
+          const int r = ty + TY * a2;
+          if (r >= nr) break;
+          const int i = ridx[a2];
+          const double li = rval[a2];
+          if (tx == 0) rhs[i] = rhs[i] - li * yj;
+          double *row = S + tri_base(i);
+          double old[MC];
+#pragma unroll
+          for (int m = 0; m < MC; ++m) old[m] = (tx + TY * m <= r) ? row[cidx[m]] : 0.0;
+#pragma unroll
+          for (int m = 0; m < MC; ++m) {
+            const int c = tx + TY * m;
+            if (c <= r) {
+              const double nv = old[m] - li * cval[m];
+              row[cidx[m]] = nv;
+              if (c == r && (nv > v || (nv == v && i < key))) { v = nv; pos = r; key = i; }
+            }
+          }
+        }
+      } else {
+        constexpr int CH = 8;  // columns loaded per batch
+        for (int r = ty; r < nr; r += kSolveBlock / TY) {
+          const int i = rem2[r];
+          const double li = lcol[r];
+          if (tx == 0) rhs[i] = rhs[i] - li * yj;
+          double *row = S + tri_base(i);
+          for (int c0 = tx; c0 <= r; c0 += TY * CH) {
+            int ci[CH];
+            double old[CH], cv[CH];
+#pragma unroll
+            for (int m = 0; m < CH; ++m) {
+              const int c = c0 + TY * m;
+              ci[m] = c <= r ? rem2[c] : 0;
+              cv[m] = c <= r ? lcol[c] : 0.0;
+            }
+#pragma unroll
+            for (int m = 0; m < CH; ++m) old[m] = (c0 + TY * m <= r) ? row[ci[m]] : 0.0;
+#pragma unroll
+            for (int m = 0; m < CH; ++m) {
+              const int c = c0 + TY * m;
+              if (c <= r) {
+                const double nv = old[m] - li * cv[m];
+                row[ci[m]] = nv;
+                if (c == r && (nv > v || (nv == v && i < key))) { v = nv; pos = r; key = i; }
+              }
+            }
+          }
+        }
       }
-      cur ^= 1;
+      wave_argmax(v, pos, key);
+      if (lane == 0) { wv[wave] = v; wp[wave] = pos; wk[wave] = key; }
+      int *t = rem;
+      rem = rem2;
+      rem2 = t;
       __syncthreads();
     }
     if (rank == k) {
-      // forward: L~ y = r~ (rows in pivot order)
-      for (int j = 0; j < k; ++j) {
-        const int pj = piv[j];
-        const double yj = rhs[pj] / S[(int64_t)pj * k + pj];
-        for (int i = tid; i < k; i += BLOCK)
-          if (step_of[i] > j) rhs[i] = rhs[i] - S[lidx(i, pj, k)] * yj;
-        if (tid == 0) y[j] = yj;
-        __syncthreads();
-      }
       // backward: L~^T lambda~ = y
-      for (int j = k - 1; j >= 0; --j) {
-        const int pj = piv[j];
-        const double lj = y[j] / S[(int64_t)pj * k + pj];
-        for (int jj = tid; jj < j; jj += BLOCK) y[jj] = y[jj] - S[lidx(pj, piv[jj], k)] * lj;
-        if (tid == 0) lam[pj] = lj;
+      if (MAT_LDS) {
+        // k <= kSolveBlock here: thread tid owns y[tid] in a register
+        const int my_p = tid < k ? piv[tid] : 0;
+        double my_y = tid < k ? y[tid] : 0.0;
+        for (int j = k - 1; j >= 0; --j) {
+          if (tid == j) {
+            const double lj = my_y * dinv[j];
+            lam[my_p] = lj;
+            y[j] = lj;
+          }
+          __syncthreads();
+          const double lj = y[j];
+          const int pj = piv[j];
+          if (tid < j) my_y = my_y - S[lp(pj, my_p)] * lj;
+        }
         __syncthreads();
+      } else {
+        for (int j = k - 1; j >= 0; --j) {
+          const int pj = piv[j];
+          const double lj = y[j] * dinv[j];
+          for (int jj = tid; jj < j; jj += kSolveBlock) y[jj] = y[jj] - S[lp(pj, piv[jj])] * lj;
+          if (tid == 0) lam[pj] = lj;
+          __syncthreads();
+        }
       }
     } else {
       if (tid == 0) atomicAdd(a.rank_def, 1);
       const int r = rank;
       // row order: pivots, then the never-pivoted indices (in index order)
-      const int *rem = sh.rem[cur];
-      for (int q = tid; q < k - r; q += BLOCK) piv[r + q] = rem[q];
+      for (int q = tid; q < k - r; q += kSolveBlock) piv[r + q] = rem[q];
       __syncthreads();
-#define LT(aa, jj) ((aa) < (jj) ? 0.0 : S[lidx(piv[(aa)], piv[(jj)], k)])
-      for (int j = tid; j < r; j += BLOCK) {  // y = L~^T r~
+#define LT(aa, jj) ((aa) < (jj) ? 0.0 : S[lp(piv[(aa)], piv[(jj)])])
+      for (int j = tid; j < r; j += kSolveBlock) {  // y = L~^T r~
         double acc = 0.0;
-        for (int aa = j; aa < k; ++aa) acc += LT(aa, j) * rhs[piv[aa]];
+        for (int aa = j; aa < k; ++aa) acc += LT(aa, j) * rr[piv[aa]];
         y[j] = acc;
       }
-      for (int64_t idx = tid; idx < (int64_t)r * r; idx += BLOCK) {  // C = L~^T L~ (lower)
-        const int j1 = (int)(idx / r), j2 = (int)(idx % r);
-        if (j2 > j1) continue;
-        double acc = 0.0;
-        for (int aa = j1; aa < k; ++aa) acc += LT(aa, j1) * LT(aa, j2);
-        Cm[(int64_t)j1 * r + j2] = acc;
-      }
+      for (int j1 = ty; j1 < r; j1 += kSolveBlock / TY)  // C = L~^T L~ (packed lower)
+        for (int j2 = tx; j2 <= j1; j2 += TY) {
+          double acc = 0.0;
+          for (int aa = j1; aa < k; ++aa) acc += LT(aa, j1) * LT(aa, j2);
+          Cm[tri_base(j1) + j2] = acc;
+        }
       __syncthreads();
-      for (int j = 0; j < r; ++j) {  // Cholesky of C (positive definite), lower
-        const double cjj = sqrt(Cm[(int64_t)j * r + j]);
+      for (int j = 0; j < r; ++j) {  // Cholesky of C (positive definite)
+        const double cjj = sqrt(Cm[tri_base(j) + j]);
         __syncthreads();
-        if (tid == 0) Cm[(int64_t)j * r + j] = cjj;
-        for (int i = j + 1 + tid; i < r; i += BLOCK) Cm[(int64_t)i * r + j] = Cm[(int64_t)i * r + j] / cjj;
+        if (tid == 0) Cm[tri_base(j) + j] = cjj;
+        for (int i = j + 1 + tid; i < r; i += kSolveBlock) Cm[tri_base(i) + j] = Cm[tri_base(i) + j] / cjj;
         __syncthreads();
-        for (int i = j + 1 + ty; i < r; i += BLOCK / TY) {
-          const double lij = Cm[(int64_t)i * r + j];
+        for (int i = j + 1 + ty; i < r; i += kSolveBlock / TY) {
+          const double lij = Cm[tri_base(i) + j];
           for (int l = j + 1 + tx; l <= i; l += TY)
-            Cm[(int64_t)i * r + l] = Cm[(int64_t)i * r + l] - lij * Cm[(int64_t)l * r + j];
+            Cm[tri_base(i) + l] = Cm[tri_base(i) + l] - lij * Cm[tri_base(l) + j];
         }
         __syncthreads();
       }
       for (int pass = 0; pass < 2; ++pass) {  // y <- C^-1 y, twice
         for (int j = 0; j < r; ++j) {
-          const double yj = y[j] / Cm[(int64_t)j * r + j];
+          const double yj = y[j] / Cm[tri_base(j) + j];
           __syncthreads();
-          for (int i = j + 1 + tid; i < r; i += BLOCK) y[i] = y[i] - Cm[(int64_t)i * r + j] * yj;
+          for (int i = j + 1 + tid; i < r; i += kSolveBlock) y[i] = y[i] - Cm[tri_base(i) + j] * yj;
           if (tid == 0) y[j] = yj;
           __syncthreads();
         }
         for (int j = r - 1; j >= 0; --j) {
-          const double lj = y[j] / Cm[(int64_t)j * r + j];
+          const double lj = y[j] / Cm[tri_base(j) + j];
           __syncthreads();
-          for (int i = tid; i < j; i += BLOCK) y[i] = y[i] - Cm[(int64_t)j * r + i] * lj;
+          for (int i = tid; i < j; i += kSolveBlock) y[i] = y[i] - Cm[tri_base(j) + i] * lj;
           if (tid == 0) y[j] = lj;
           __syncthreads();
         }
       }
-      for (int aa = tid; aa < k; aa += BLOCK) {  // lambda~ = L~ u
+      for (int aa = tid; aa < k; aa += kSolveBlock) {  // lambda~ = L~ u
         double acc = 0.0;
         const int jm = aa < r - 1 ? aa : r - 1;
         for (int j = 0; j <= jm; ++j) acc += LT(aa, j) * y[j];
@@ -484,17 +791,36 @@ __global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a, int kmin, int kmax
 #undef LT
     }
     __syncthreads();
-    for (int i = tid; i < k; i += BLOCK) a.lambda[a.order[st + i]] = lam[i];
+    for (int i = tid; i < k; i += kSolveBlock) a.lambda[a.order[st + i]] = lam[i];
     __syncthreads();
-#undef CON
   }
+}
+
+template <bool MAT_LDS, bool VEC_LDS>
+static void launch_class(const SolveArgs &a, int kmin, int kcap, int grid, hipStream_t s) {
+  const size_t bytes = MAT_LDS ? zone_lds_bytes(true, kcap) : (VEC_LDS ? zone_vec_bytes(kcap) : 0) + 4 * 16 + 64;
+  static bool attr_set = false;  // the attribute is per function
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve<MAT_LDS, VEC_LDS>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  k_solve<MAT_LDS, VEC_LDS><<<grid, kSolveBlock, bytes, s>>>(a, kmin, kcap);
 }
 
 void launch_solve(const SolveArgs &a, hipStream_t s) {
   if (a.nzones <= 0) return;
   const int grid = a.nslots < a.nzones ? a.nslots : a.nzones;
-  k_solve<64><<<grid, 64, 0, s>>>(a, 0, kSmallZone);
-  if (a.maxk > kSmallZone) k_solve<kBigBlock><<<grid, kBigBlock, 0, s>>>(a, kSmallZone, kMaxZoneLds);
+  const int kl = a.maxk < kZoneLds ? a.maxk : kZoneLds;
+  launch_class<true, true>(a, 0, kl, grid, s);
+  if (a.maxk > kZoneLds && a.maxk <= kZoneVecLds) launch_class<false, true>(a, kZoneLds, a.maxk, grid, s);
+  if (a.maxk > kZoneVecLds) launch_class<false, false>(a, kZoneLds, a.maxk, grid, s);
+}
+
+size_t solve_slot_doubles(int maxk) {
+  const int64_t k = maxk;
+  // matrix (tiled or packed), C (packed), then the per-zone arrays
+  return (size_t)(zone_mat_doubles(maxk) + k * (k + 1) / 2 + (int64_t)(zone_vec_bytes(maxk) / 8) + 16);
 }
 
 // ------------------------------------------------------------------ update
