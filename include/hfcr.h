@@ -140,7 +140,7 @@ typedef struct {
   int32_t pivoted_zones;     /* zones solved by the pivoted fallback (a zone
                                 whose unpivoted pivots fell below 1e-6 of
                                 its largest diagonal entry)                 */
-  int32_t reserved_stat;
+  int32_t max_query_path;    /* most BVH nodes any one query fetched        */
   double stage_ms[HFCR_STAGES];     /* with HFCR_FLAG_TIMING, else 0        */
   int32_t stage_calls[HFCR_STAGES]; /* timed intervals per stage            */
   int32_t round_hits[HFCR_STAT_ROUNDS];
@@ -164,6 +164,13 @@ typedef struct {
 } hfcr_result;
 
 typedef struct hfcr_ctx hfcr_ctx;
+
+/* Launch schedule of a context (results never depend on it). */
+typedef struct {
+  int32_t trav_block; /* traversal workgroup size: 64, 128 or 256 (128)     */
+  int32_t trav_warm;  /* 1: warm the L2 with the face BVH first (1)         */
+  int32_t reserved0, reserved1;
+} hfcr_tuning;
 
 /* Fill *opts with the defaults above. */
 void hfcr_default_opts(hfcr_opts *opts);
@@ -193,6 +200,12 @@ hfcr_status hfcr_detect(hfcr_ctx *ctx, const hfcr_mesh *a, const hfcr_mesh *b,
 hfcr_status hfcr_resolve(hfcr_ctx *ctx, const hfcr_mesh *a, const hfcr_mesh *b,
                          int32_t orientation, double d, const hfcr_opts *opts,
                          hfcr_result *res, void *stream);
+
+/* Read or replace the context's launch schedule (hfcr_tuning).  Every
+ * schedule gives identical results; only speed differs.  Returns
+ * HFCR_E_INVALID for an unsupported value. */
+hfcr_status hfcr_get_tuning(const hfcr_ctx *ctx, hfcr_tuning *tuning);
+hfcr_status hfcr_set_tuning(hfcr_ctx *ctx, const hfcr_tuning *tuning);
 
 /* Diagnostic: signs of orient(a,b,c,p) for n point quadruples pts (device,
  * [n][4][3] float64: a, b, c, p) into out (device, [n] int32).  tier 0: the

@@ -41,7 +41,7 @@ STAGES = 8
 STAGE_NAMES = ["setup", "refit", "traverse", "exact", "stencils", "zones", "solve", "update"]
 
 EXPORTED = ["hfcr_default_opts", "hfcr_create", "hfcr_destroy", "hfcr_last_error", "hfcr_detect",
-            "hfcr_resolve", "hfcr_test_orient"]
+            "hfcr_resolve", "hfcr_test_orient", "hfcr_get_tuning", "hfcr_set_tuning"]
 
 
 class Mesh(ctypes.Structure):
@@ -63,7 +63,7 @@ class Stats(ctypes.Structure):
                 ("exact_tests", ctypes.c_int64), ("f32_ambiguous", ctypes.c_int64),
                 ("max_zone", ctypes.c_int32), ("rank_deficient", ctypes.c_int32),
                 ("node_visits", ctypes.c_int64), ("pivoted_zones", ctypes.c_int32),
-                ("reserved_stat", ctypes.c_int32),
+                ("max_query_path", ctypes.c_int32),
                 ("stage_ms", ctypes.c_double * STAGES), ("stage_calls", ctypes.c_int32 * STAGES),
                 ("round_hits", ctypes.c_int32 * STAT_ROUNDS),
                 ("round_stencils", ctypes.c_int32 * STAT_ROUNDS),
@@ -78,12 +78,17 @@ class Stats(ctypes.Structure):
             "candidates": self.candidates, "exact_tests": self.exact_tests,
             "f32_ambiguous": self.f32_ambiguous, "max_zone": self.max_zone,
             "rank_deficient": self.rank_deficient, "node_visits": self.node_visits,
-            "pivoted_zones": self.pivoted_zones,
+            "pivoted_zones": self.pivoted_zones, "max_query_path": self.max_query_path,
             "stage_ms": {STAGE_NAMES[i]: self.stage_ms[i] for i in range(STAGES)},
             "stage_calls": {STAGE_NAMES[i]: self.stage_calls[i] for i in range(STAGES)},
             "round_hits": list(self.round_hits[:n]), "round_stencils": list(self.round_stencils[:n]),
             "round_zones": list(self.round_zones[:n]), "round_max_zone": list(self.round_max_zone[:n]),
         }
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("trav_block", ctypes.c_int32), ("trav_warm", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -120,6 +125,10 @@ def lib():
         L.hfcr_resolve.restype = ctypes.c_int
         L.hfcr_test_orient.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
         L.hfcr_test_orient.restype = ctypes.c_int
+        L.hfcr_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.hfcr_get_tuning.restype = ctypes.c_int
+        L.hfcr_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.hfcr_set_tuning.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -171,6 +180,21 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        st = self._L.hfcr_get_tuning(self._h, ctypes.byref(t))
+        if st != HFCR_OK:
+            raise HfcrError(st, self.last_error())
+        return {"trav_block": t.trav_block, "trav_warm": t.trav_warm}
+
+    def set_tuning(self, **kw) -> None:
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = Tuning(int(cur["trav_block"]), int(cur["trav_warm"]), 0, 0)
+        st = self._L.hfcr_set_tuning(self._h, ctypes.byref(t))
+        if st != HFCR_OK:
+            raise HfcrError(st, self.last_error())
 
     def last_error(self) -> str:
         return self._L.hfcr_last_error(self._h).decode()

@@ -38,6 +38,8 @@ struct Counters {
   unsigned long long f32_unsure;
   unsigned long long exact;
   unsigned long long visits;
+  uint32_t max_path;
+  uint32_t pad2;
 };
 
 struct Timer {
@@ -76,6 +78,7 @@ struct hfcr_ctx {
   std::vector<Timer> timers;
   std::vector<hipEvent_t> free_events;
   bool timing = false;
+  hfcr_tuning tune{128, 1, 0, 0};
 };
 
 namespace {
@@ -331,11 +334,12 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
     out.f32_unsure = &dc->f32_unsure;
     out.exact = &dc->exact;
     out.visits = &dc->visits;
+    out.max_path = &dc->max_path;
     out.overflow = &dc->overflow;
-    out.warm = 1;
+    out.warm = c->tune.trav_warm;
     {
       Scope t(c, 2);
-      launch_traverse(E, F, dir, P.tier0, P.hl, out, c->s);
+      launch_traverse(E, F, dir, P.tier0, P.hl, out, c->tune.trav_block, c->s);
     }
     {
       Scope t(c, 3);
@@ -670,6 +674,7 @@ hfcr_status hfcr_detect(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, int
       st->exact_tests = (int64_t)c->hctr->exact;
       st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
       st->node_visits = (int64_t)c->hctr->visits;
+      st->max_query_path = (int32_t)c->hctr->max_path;
       st->converged = st->hits0 == 0;
       st->residual_hits = st->hits0;
     }
@@ -767,6 +772,7 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
       st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
       st->rank_deficient = c->hctr->rank_def;
       st->node_visits = (int64_t)c->hctr->visits;
+      st->max_query_path = (int32_t)c->hctr->max_path;
       st->pivoted_zones = c->hctr->pivoted;
     }
     finish_timing(c, st);
@@ -774,6 +780,26 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
     if (truncated) return HFCR_E_CAPACITY;
     return converged ? HFCR_OK : HFCR_NOT_CONVERGED;
   });
+}
+
+hfcr_status hfcr_get_tuning(const hfcr_ctx *c, hfcr_tuning *t) {
+  if (!c || !t) return HFCR_E_INVALID;
+  *t = c->tune;
+  return HFCR_OK;
+}
+
+hfcr_status hfcr_set_tuning(hfcr_ctx *c, const hfcr_tuning *t) {
+  if (!c || !t) return HFCR_E_INVALID;
+  if (t->trav_block != 64 && t->trav_block != 128 && t->trav_block != 256) {
+    c->err = "trav_block must be 64, 128 or 256";
+    return HFCR_E_INVALID;
+  }
+  if (t->trav_warm != 0 && t->trav_warm != 1) {
+    c->err = "trav_warm must be 0 or 1";
+    return HFCR_E_INVALID;
+  }
+  c->tune = *t;
+  return HFCR_OK;
 }
 
 hfcr_status hfcr_test_orient(hfcr_ctx *c, const double *pts, int64_t n, int32_t tier, int32_t *out, void *stream) {

@@ -14,7 +14,6 @@
 
 namespace hfcr {
 
-constexpr int kTravBlock = 128;
 constexpr int kStack = 64;  // tree depth <= 30 Morton bits + 24 index bits + 1
 
 __device__ inline uint64_t lanemask_lt() {
@@ -52,9 +51,16 @@ __device__ inline unsigned warm_l2(const void *p, int64_t bytes, unsigned acc) {
   const int64_t per = (n16 + slices - 1) / slices;
   const int64_t lo = slice * per, hi = lo + per < n16 ? lo + per : n16;
   const uint4 *q = reinterpret_cast<const uint4 *>(p);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const uint4 v = q[i];
-    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  constexpr int U = 8;  // independent loads in flight per thread
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (int64_t)U * blockDim.x) {
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * blockDim.x;
+      v[u] = i < hi ? q[i] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
   }
   return acc;
 }
@@ -90,31 +96,35 @@ __device__ inline void load_point(const double *x64, const float *x32, int nv, i
   }
 }
 
+__device__ inline P3f load_f32(const float *x32, int nv, int i) {
+  return P3f{x32[i], x32[(int64_t)nv + i], x32[2 * (int64_t)nv + i]};
+}
+
+__device__ inline P3d load_f64(const double *x64, int nv, int i) {
+  return P3d{x64[i], x64[(int64_t)nv + i], x64[2 * (int64_t)nv + i]};
+}
+
 // Narrow phase for one candidate: returns 0/1/2, or kHitUnsure after both filters.
+// In the float32 tier the float64 coordinates are loaded only when the
+// float32 filter cannot settle the test.
 template <bool F32, bool TIER0>
-__device__ inline int narrow(const TravArgs &A, P3f pf, P3f qf, P3d pd, P3d qd, int4 t, unsigned long long &unsure32) {
-  P3f af, bf, cf;
-  P3d ad, bd, cd;
+__device__ inline int narrow(const TravArgs &A, int4 qe, P3f pf, P3f qf, int4 t, unsigned long long &unsure32) {
   if (TIER0) {
-    load_point<true>(A.fx64, A.fx32, A.fnv, t.x, af, ad);
-    load_point<true>(A.fx64, A.fx32, A.fnv, t.y, bf, bd);
-    load_point<true>(A.fx64, A.fx32, A.fnv, t.z, cf, cd);
-    int r = ef_test_f32(pf, qf, af, bf, cf);
+    const P3f af = load_f32(A.fx32, A.fnv, t.x), bf = load_f32(A.fx32, A.fnv, t.y), cf = load_f32(A.fx32, A.fnv, t.z);
+    const int r = ef_test_f32(pf, qf, af, bf, cf);
     if (r != kHitUnsure) return r;
     ++unsure32;
-  } else {
-    load_point<false>(A.fx64, A.fx32, A.fnv, t.x, af, ad);
-    load_point<false>(A.fx64, A.fx32, A.fnv, t.y, bf, bd);
-    load_point<false>(A.fx64, A.fx32, A.fnv, t.z, cf, cd);
   }
+  const P3d pd = load_f64(A.ex64, A.env, qe.x), qd = load_f64(A.ex64, A.env, qe.y);
+  const P3d ad = load_f64(A.fx64, A.fnv, t.x), bd = load_f64(A.fx64, A.fnv, t.y), cd = load_f64(A.fx64, A.fnv, t.z);
   return ef_test_f64<false>(pd, qd, ad, bd, cd);
 }
 
-template <bool F32, bool TIER0>
-__global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs A) {
-  __shared__ int stack[kStack][kTravBlock];
+template <bool F32, bool TIER0, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
+  __shared__ int stack[kStack][BLOCK];
   const int tid = threadIdx.x;
-  const int qi = blockIdx.x * kTravBlock + tid;
+  const int qi = blockIdx.x * BLOCK + tid;
   if (A.warm && A.nt > 1) {
     unsigned acc = warm_l2(A.nodes, (int64_t)(A.nt - 1) * sizeof(BvhNode), 0u);
     acc = warm_l2(A.leaf_tri, (int64_t)A.nt * sizeof(int4), acc);
@@ -129,8 +139,13 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs A) {
   P3d pd{}, qd{};
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   if (valid) {
-    load_point<F32>(A.ex64, A.ex32, A.env, qe.x, pf, pd);
-    load_point<F32>(A.ex64, A.ex32, A.env, qe.y, qf, qd);
+    if (F32) {
+      pf = load_f32(A.ex32, A.env, qe.x);
+      qf = load_f32(A.ex32, A.env, qe.y);
+    } else {
+      pd = load_f64(A.ex64, A.env, qe.x);
+      qd = load_f64(A.ex64, A.env, qe.y);
+    }
     if (F32) {
       lo[0] = fminf(pf.x, qf.x); hi[0] = fmaxf(pf.x, qf.x);
       lo[1] = fminf(pf.y, qf.y); hi[1] = fmaxf(pf.y, qf.y);
@@ -146,13 +161,15 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs A) {
   // A single face has no internal node: test it directly.
   int pending_leaf = (alive && A.nt == 1) ? 0 : -1;
   if (A.nt == 1) alive = false;
-  int node = 0, sp = 0;
+  int node = 0, sp = 0, top = -1;
+  unsigned path = 0;
   const uint64_t dir_bits = (uint64_t)A.dir << (A.lay.bits_e + A.lay.bits_f);
   while (true) {
     int leaf_a = pending_leaf, leaf_b = -1;
     pending_leaf = -1;
     if (alive) {
       ++nvisit;
+      ++path;
       const BvhNode nd = A.nodes[node];
       const bool o0 = box_overlap(lo, hi, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
       const bool o1 = box_overlap(lo, hi, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
@@ -160,34 +177,42 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs A) {
       bool i0 = o0 && c0 >= 0, i1 = o1 && c1 >= 0;
       if (o0 && c0 < 0) leaf_a = ~c0;
       if (o1 && c1 < 0) leaf_b = ~c1;
+      // the most recently deferred node stays in a register (top); older
+      // ones spill to the LDS stack, so a pop after a push costs no LDS load
       if (i0 && i1) {
-        if (sp >= kStack) {
-          atomicOr(A.out.overflow, 1);
-          alive = false;
-        } else {
-          stack[sp++][tid] = c1;
-          node = c0;
+        if (top >= 0) {
+          if (sp >= kStack) {
+            atomicOr(A.out.overflow, 1);
+            alive = false;
+          } else {
+            stack[sp++][tid] = top;
+          }
         }
+        top = c1;
+        node = c0;
       } else if (i0) {
         node = c0;
       } else if (i1) {
         node = c1;
-      } else if (sp > 0) {
-        node = stack[--sp][tid];
+      } else if (top >= 0) {
+        node = top;
+        top = sp > 0 ? stack[--sp][tid] : -1;
       } else {
         alive = false;
       }
     }
-    // narrow phase of up to two leaves found at this step
+    // narrow phase of up to two leaves found at this step (skipped by the
+    // whole wavefront when no lane reached a leaf)
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
+      if (!__any((k == 0 ? leaf_a : leaf_b) >= 0)) continue;
       const int leaf = k == 0 ? leaf_a : leaf_b;
       int res = 0;
       int4 t = make_int4(0, 0, 0, 0);
       if (leaf >= 0) {
         t = A.leaf_tri[leaf];
         ++ncand;
-        res = narrow<F32, TIER0>(A, pf, qf, pd, qd, t, unsure32);
+        res = narrow<F32, TIER0>(A, qe, pf, qf, t, unsure32);
       }
       const bool is_hit = res == 1 || res == 2;
       const uint32_t slot = wave_append(A.out.count, is_hit);
@@ -212,6 +237,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravArgs A) {
     if (unsure32) atomicAdd(A.out.f32_unsure, unsure32);
     if (nvisit) atomicAdd(A.out.visits, nvisit);
   }
+  for (int off = 32; off > 0; off >>= 1) path = max(path, (unsigned)__shfl_xor((int)path, off));
+  if (__lane_id() == 0 && path) atomicMax(A.out.max_path, path);
 }
 
 static TravArgs make_args(const MeshDev &E, const MeshDev &F, int dir, HitLayout lay, const DcdOut &out) {
@@ -235,18 +262,28 @@ static TravArgs make_args(const MeshDev &E, const MeshDev &F, int dir, HitLayout
   return a;
 }
 
-void launch_traverse(const MeshDev &E, const MeshDev &F, int dir, bool tier0, HitLayout lay, const DcdOut &out,
-                     hipStream_t s) {
-  if (E.ne <= 0 || F.nt <= 0) return;
-  TravArgs a = make_args(E, F, dir, lay, out);
-  const unsigned grid = grid_for(E.ne, kTravBlock);
+template <int BLOCK>
+static void launch_traverse_b(const MeshDev &E, const MeshDev &F, bool tier0, const TravArgs &a, hipStream_t s) {
+  const unsigned grid = grid_for(E.ne, BLOCK);
   const bool f32 = E.f32 && F.f32 && E.x32 && F.x32;
   if (f32 && tier0 && E.small_coords && F.small_coords)
-    k_traverse<true, true><<<grid, kTravBlock, 0, s>>>(a);
+    k_traverse<true, true, BLOCK><<<grid, BLOCK, 0, s>>>(a);
   else if (f32)
-    k_traverse<true, false><<<grid, kTravBlock, 0, s>>>(a);
+    k_traverse<true, false, BLOCK><<<grid, BLOCK, 0, s>>>(a);
   else
-    k_traverse<false, false><<<grid, kTravBlock, 0, s>>>(a);
+    k_traverse<false, false, BLOCK><<<grid, BLOCK, 0, s>>>(a);
+}
+
+void launch_traverse(const MeshDev &E, const MeshDev &F, int dir, bool tier0, HitLayout lay, const DcdOut &out,
+                     int block, hipStream_t s) {
+  if (E.ne <= 0 || F.nt <= 0) return;
+  TravArgs a = make_args(E, F, dir, lay, out);
+  if (block <= 64)
+    launch_traverse_b<64>(E, F, tier0, a, s);
+  else if (block <= 128)
+    launch_traverse_b<128>(E, F, tier0, a, s);
+  else
+    launch_traverse_b<256>(E, F, tier0, a, s);
 }
 
 // ------------------------------------------------------------ exact tier

@@ -37,11 +37,12 @@ struct DcdOut {
   unsigned long long *f32_unsure;
   unsigned long long *exact;    // exact-tier tests
   unsigned long long *visits;   // BVH nodes fetched
+  unsigned *max_path;           // longest single-query node count
   int *overflow;         // traversal stack overflow flag
   int warm;              // warm the L2 before traversing
 };
 void launch_traverse(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, bool tier0, HitLayout lay,
-                     const DcdOut &out, hipStream_t s);
+                     const DcdOut &out, int block, hipStream_t s);
 void launch_exact(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, HitLayout lay, const DcdOut &out,
                   hipStream_t s);
 void launch_write_hits(const uint64_t *keys, const uint32_t *vals, int64_t n, HitLayout lay, const int2 *edges_a,
