@@ -137,32 +137,26 @@ def icosphere(subdiv: int, radius: float = 1.0):
 
 def uv_sphere(n_rings: int, n_seg: int, radius: float = 1.0):
     """Latitude/longitude sphere with poles; 2*n_seg*(n_rings-1) triangles."""
-    verts = [(0.0, 0.0, radius)]
-    for i in range(1, n_rings):
-        th = math.pi * i / n_rings
-        for j in range(n_seg):
-            ph = 2.0 * math.pi * j / n_seg
-            verts.append((radius * math.sin(th) * math.cos(ph),
-                          radius * math.sin(th) * math.sin(ph),
-                          radius * math.cos(th)))
-    verts.append((0.0, 0.0, -radius))
-    south = len(verts) - 1
+    th = math.pi * np.arange(1, n_rings) / n_rings
+    ph = 2.0 * math.pi * np.arange(n_seg) / n_seg
+    T, PH = np.meshgrid(th, ph, indexing="ij")
+    ring_pts = np.stack([radius * np.sin(T) * np.cos(PH), radius * np.sin(T) * np.sin(PH),
+                         radius * np.cos(T)], axis=-1).reshape(-1, 3)
+    pos = np.concatenate([[[0.0, 0.0, radius]], ring_pts, [[0.0, 0.0, -radius]]]).astype(np.float64)
+    south = len(pos) - 1
 
     def ring(i, j):
         return 1 + (i - 1) * n_seg + (j % n_seg)
 
-    faces = []
-    for j in range(n_seg):
-        faces.append((0, ring(1, j), ring(1, j + 1)))
-    for i in range(1, n_rings - 1):
-        for j in range(n_seg):
-            a, b = ring(i, j), ring(i, j + 1)
-            c, d = ring(i + 1, j), ring(i + 1, j + 1)
-            faces += [(a, c, d), (a, d, b)]
-    for j in range(n_seg):
-        faces.append((south, ring(n_rings - 1, j + 1), ring(n_rings - 1, j)))
-    pos = np.array(verts, dtype=np.float64)
-    return pos, _orient_outward(pos, np.array(faces, dtype=np.int32))
+    j = np.arange(n_seg)
+    north = np.stack([np.zeros(n_seg, np.int64), ring(1, j), ring(1, j + 1)], -1)
+    ii, jj = np.meshgrid(np.arange(1, n_rings - 1), j, indexing="ij")
+    a, b = ring(ii, jj), ring(ii, jj + 1)
+    c, d = ring(ii + 1, jj), ring(ii + 1, jj + 1)
+    mid = np.stack([np.stack([a, c, d], -1), np.stack([a, d, b], -1)], axis=2).reshape(-1, 3)
+    southf = np.stack([np.full(n_seg, south), ring(n_rings - 1, j + 1), ring(n_rings - 1, j)], -1)
+    faces = np.concatenate([north, mid, southf]).astype(np.int32)
+    return pos, _orient_outward(pos, faces)
 
 
 def grid_sheet(nx: int, ny: int, side: float, z: float = 0.0):
@@ -176,15 +170,11 @@ def grid_sheet(nx: int, ny: int, side: float, z: float = 0.0):
     X, Y = np.meshgrid(xs, ys, indexing="ij")
     pos = np.stack([X.ravel(), Y.ravel(), np.full(nx * ny, z)], axis=1)
 
-    def vid(i, j):
-        return i * ny + j
-
-    faces = []
-    for i in range(nx - 1):
-        for j in range(ny - 1):
-            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
-            faces += [(a, b, c), (a, c, d)]
-    return pos, np.array(faces, dtype=np.int32)
+    ii, jj = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), indexing="ij")
+    a, b = ii * ny + jj, (ii + 1) * ny + jj
+    c, d = (ii + 1) * ny + jj + 1, ii * ny + jj + 1
+    faces = np.stack([np.stack([a, b, c], -1), np.stack([a, c, d], -1)], axis=2).reshape(-1, 3)
+    return pos, faces.astype(np.int32)
 
 
 def torus(nu: int, nv: int, R: float = 1.0, r: float = 0.3):
@@ -197,15 +187,13 @@ def torus(nu: int, nv: int, R: float = 1.0, r: float = 0.3):
     y = (R + r * np.cos(ph)) * np.sin(th)
     z = r * np.sin(ph) * np.ones_like(th)
     pos = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
-    faces = []
-    for a_i in range(nu):
-        for a_j in range(nv):
-            a = a_i * nv + a_j
-            b = ((a_i + 1) % nu) * nv + a_j
-            c = ((a_i + 1) % nu) * nv + (a_j + 1) % nv
-            d = a_i * nv + (a_j + 1) % nv
-            faces += [(a, b, c), (a, c, d)]
-    return pos, _orient_outward(pos, np.array(faces, dtype=np.int32))
+    ii, jj = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    a = ii * nv + jj
+    b = ((ii + 1) % nu) * nv + jj
+    c = ((ii + 1) % nu) * nv + (jj + 1) % nv
+    d = ii * nv + (jj + 1) % nv
+    faces = np.stack([np.stack([a, b, c], -1), np.stack([a, c, d], -1)], axis=2).reshape(-1, 3)
+    return pos, _orient_outward(pos, faces.astype(np.int32))
 
 
 def rot_x(deg: float) -> np.ndarray:
@@ -281,6 +269,66 @@ def random_small_pair(seed: int, kind: str = "sphere_sheet") -> Pair:
     pa = pa + rng.normal(0.0, 0.01, pa.shape)
     pb = pb + rng.normal(0.0, 0.01, pb.shape)
     return Pair(f"small_tt_{seed}", pa, ta, pb, tb, ORIENT_BOTH, 1e-3, F32, 0).cast()
+
+
+def _loguniform(rng: np.random.Generator, lo: float, hi: float) -> float:
+    return float(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+
+
+def uv_sphere_f(target: float, radius: float = 1.0):
+    """UV sphere with about `target` triangles (2 * n_seg * (n_rings - 1))."""
+    n_rings = max(3, int(round(math.sqrt(target / 4.0))) + 1)
+    n_seg = max(3, int(round(target / (2.0 * (n_rings - 1)))))
+    return uv_sphere(n_rings, n_seg, radius)
+
+
+def sheet_f(target: float, side: float, z: float):
+    """Square sheet of the given side with about `target` triangles."""
+    a = max(1, int(round(math.sqrt(target / 2.0))))
+    b = max(1, int(round(target / (2.0 * a))))
+    return grid_sheet(a + 1, b + 1, side, z)
+
+
+def torus_f(target: float, R: float = 1.0, r: float = 0.3):
+    """Torus with about `target` triangles and twice as many major as minor segments."""
+    nv = max(3, int(round(math.sqrt(target / 4.0))))
+    nu = max(3, int(round(target / (2.0 * nv))))
+    return torus(nu, nv, R, r)
+
+
+def pair_set(seed: int = 4, n: int = 256, f_lo: float = 500.0, f_hi: float = 50000.0,
+             dtype: str = F32, tier: int = 0) -> list:
+    """A batch of independent pairs of mixed kinds and sizes.
+
+    Even entries are sphere-sheet pairs (UV sphere of radius 1, oriented, as
+    mesh B; a square sheet of side 2.5 as mesh A in the plane at distance
+    1 - depth from the sphere's centre), odd entries torus-torus pairs (both
+    oriented, R = 1, r = 0.3, the second rotated 90 degrees about x and
+    shifted 1.4 + depth along x).  Each mesh has a triangle count drawn
+    log-uniformly from [f_lo, f_hi]; depth ~ U[0.1, 0.4]; each pair is then
+    moved by one uniform random rotation and a translation ~ U[-5, 5]^3.
+    Every pair draws from its own stream, SeedSequence(seed).spawn(n)[k].
+    """
+    pairs = []
+    for k, ss in enumerate(np.random.SeedSequence(seed).spawn(n)):
+        rng = np.random.default_rng(ss)
+        depth = float(rng.uniform(0.1, 0.4))
+        fa, fb = _loguniform(rng, f_lo, f_hi), _loguniform(rng, f_lo, f_hi)
+        if k % 2 == 0:
+            pb, tb = uv_sphere_f(fb)
+            pa, ta = sheet_f(fa, 2.5, 1.0 - depth)
+            kind, orient = "ss", ORIENT_B
+        else:
+            pa, ta = torus_f(fa)
+            pb, tb = torus_f(fb)
+            pb = pb @ rot_x(90.0).T + np.array([1.4 + depth, 0.0, 0.0])
+            kind, orient = "tt", ORIENT_BOTH
+        rot = random_rotation(rng)
+        shift = rng.uniform(-5.0, 5.0, 3)
+        pa = pa @ rot.T + shift
+        pb = pb @ rot.T + shift
+        pairs.append(Pair(f"set{seed}_{k}_{kind}", pa, ta, pb, tb, orient, 1e-3, dtype, tier).cast())
+    return pairs
 
 
 def workload(name: str, **kw) -> Pair:

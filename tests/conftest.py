@@ -21,3 +21,11 @@ def hfcr_ctx():
     ctx = hf.Context(0)
     yield ctx
     ctx.close()
+
+
+def pytest_runtest_logstart(nodeid, location):
+    # name every GPU case on its own line before it runs, so that a run that
+    # ends abruptly still shows which case was on the device
+    if "gpu" in nodeid:
+        sys.__stderr__.write(f"[start] {nodeid}\n")
+        sys.__stderr__.flush()
