@@ -50,6 +50,77 @@ def traverse_bytes(pair, ne_a: int, ne_b: int, launches_dir: dict) -> float:
     return sum(per[d] * n for d, n in launches_dir.items())
 
 
+def progress(msg: str) -> None:
+    """One line of progress on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_batch(ctx, args) -> dict:
+    """Resolved pairs/s of the mixed pair set: batched float32-filtered form vs the plain form.
+
+    Batched: one hfcr_resolve_batch call over every pair (float32 storage,
+    float32-filtered predicates, pairs in flight on their own streams).
+    Plain: the same pairs resolved one at a time with float64 storage and the
+    float64 filter.  Both use the same round budget.
+    """
+    import dataclasses
+
+    import torch
+
+    import meshgen
+    import paper_1409_2081_amd as hf
+
+    progress(f"batch: generating {args.batch_pairs} pairs")
+    pairs = meshgen.pair_set(seed=4, n=args.batch_pairs)
+    items = [hf.pair_item(p, "cuda:0") for p in pairs]
+    plain = [hf.pair_item(dataclasses.replace(p, dtype=meshgen.F64, tier=1).cast(), "cuda:0") for p in pairs]
+    kw = dict(max_rounds=args.rounds, want_lists=False)
+    progress("batch: warm-up call")
+    t = time.perf_counter()
+    ctx.resolve_batch(items, tier=0, **kw)  # warm-up (creates the workers)
+    torch.cuda.synchronize()
+    progress(f"batch: warm-up call took {time.perf_counter() - t:.2f} s")
+    t = time.perf_counter()
+    for k in range(args.batch_steps):
+        b = ctx.resolve_batch(items, tier=0, timing=True, **kw)
+        progress(f"batch: timed call {k + 1}/{args.batch_steps} done")
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t) / args.batch_steps
+    for it in plain[:4]:
+        ctx.resolve(it["pos_a"], it["tri_a"], it["pos_b"], it["tri_b"], it["orientation"], it["d"], tier=1, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain_status, plain_ms = [], []
+    for k, it in enumerate(plain):
+        ts = time.perf_counter()
+        g = ctx.resolve(it["pos_a"], it["tri_a"], it["pos_b"], it["tri_b"], it["orientation"], it["d"], tier=1,
+                        raise_on_error=False, **kw)
+        plain_status.append(g["status"])
+        plain_ms.append(1e3 * (time.perf_counter() - ts))
+        if (k + 1) % 32 == 0:
+            progress(f"plain: {k + 1}/{len(plain)} pairs, {time.perf_counter() - t:.1f} s")
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    n = len(pairs)
+    st = [p["status"] for p in b["pairs"]]
+    return {
+        "workload": f"{n} mixed pairs (half sphere-sheet, half linked tori), triangles per mesh log-uniform "
+                    f"in [500, 50000], depth U[0.1, 0.4], random rigid motions, seed 4; "
+                    f"{sum(len(p.tri_a) + len(p.tri_b) for p in pairs)} triangles in all",
+        "max_rounds": args.rounds, "workers": ctx.get_tuning()["batch_workers"],
+        "batched_pairs_per_s": n / tb, "batched_ms_per_call": 1e3 * tb,
+        "plain_f64_pairs_per_s": n / tp, "plain_f64_ms_total": 1e3 * tp,
+        "speedup_vs_plain": tp / tb,
+        "batched_converged": sum(s == hf.HFCR_OK for s in st),
+        "batched_not_converged": sum(s == hf.HFCR_NOT_CONVERGED for s in st),
+        "batched_failed": sum(s < 0 for s in st),
+        "plain_converged": sum(s == hf.HFCR_OK for s in plain_status),
+        "plain_ms_p50": sorted(plain_ms)[len(plain_ms) // 2], "plain_ms_max": max(plain_ms),
+        "batched_candidates": b["stats"]["candidates"], "batched_max_zone": b["stats"]["max_zone"],
+        "batched_stage_ms_summed_over_pairs": b["stats"]["stage_ms"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +130,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU-oracle sample length (whole steps are repeated)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-pairs", type=int, default=256,
+                    help="pairs of the mixed pair set in the batched measurement (0: skip it)")
+    ap.add_argument("--batch-steps", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -76,6 +150,7 @@ def main():
     tens = hf.pair_tensors(pair, "cuda:0")
     kw = dict(tier=pair.tier, max_rounds=args.rounds, want_lists=False)
 
+    progress("linked tori: warm-up")
     for _ in range(args.warmup):
         ctx.resolve(*tens, pair.orientation, pair.d, **kw)
     torch.cuda.synchronize()
@@ -144,10 +219,15 @@ def main():
         "roofline": roofline,
     }
 
+    progress(f"linked tori: {args.steps} steps in {wall:.2f} s")
+    if args.batch_pairs > 0:
+        out["batch"] = bench_batch(ctx, args)
+
     if not args.no_cpu:
         import oracle
         nthreads = min(os.cpu_count() or 1, 16)
         oracle.lib()
+        progress("cpu oracle sample")
         t = time.perf_counter()
         n_steps, cand_cpu = 0, 0
         while True:

@@ -167,10 +167,29 @@ typedef struct hfcr_ctx hfcr_ctx;
 
 /* Launch schedule of a context (results never depend on it). */
 typedef struct {
-  int32_t trav_block; /* traversal workgroup size: 64, 128 or 256 (128)     */
-  int32_t trav_warm;  /* 1: warm the L2 with the face BVH first (1)         */
-  int32_t reserved0, reserved1;
+  int32_t trav_block;    /* traversal workgroup size: 64, 128 or 256 (128)  */
+  int32_t trav_warm;     /* 1: warm the L2 with the face BVH first (1)      */
+  int32_t batch_workers; /* pairs in flight at once in the batch calls,
+                            each on its own stream, 1..64 (8)               */
+  int32_t reserved;
 } hfcr_tuning;
+
+/* One mesh pair of a batch call.  Inputs as for hfcr_resolve; `status` and
+ * the buffers of `res` receive this pair's results. */
+typedef struct {
+  hfcr_mesh a;
+  hfcr_mesh b;
+  int32_t orientation;       /* hfcr_orientation of this pair                 */
+  int32_t status;            /* out: this pair's hfcr_status                  */
+  double d;                  /* post-response distance (Eq. 8), finite, >= 0  */
+  const double *inv_mass_a;  /* device [a.nv] inverse masses, or NULL for 1  */
+  const double *inv_mass_b;  /* device [b.nv] or NULL                        */
+  hfcr_result res;           /* this pair's outputs and stats, as for
+                                hfcr_resolve                                */
+} hfcr_pair;
+
+/* Largest number of pairs in one batch call. */
+#define HFCR_MAX_BATCH 65536
 
 /* Fill *opts with the defaults above. */
 void hfcr_default_opts(hfcr_opts *opts);
@@ -200,6 +219,33 @@ hfcr_status hfcr_detect(hfcr_ctx *ctx, const hfcr_mesh *a, const hfcr_mesh *b,
 hfcr_status hfcr_resolve(hfcr_ctx *ctx, const hfcr_mesh *a, const hfcr_mesh *b,
                          int32_t orientation, double d, const hfcr_opts *opts,
                          hfcr_result *res, void *stream);
+
+/* The repair loop of hfcr_resolve (Section 3) for npairs independent mesh
+ * pairs in one call.  Pairs are resolved concurrently: up to
+ * tuning.batch_workers pairs are in flight at once, each on an internal
+ * stream of its own, so the launches and waits of different pairs overlap.
+ * Every pair runs the single-pair path, so its positions, lists and stats are
+ * bit-identical to hfcr_resolve on that pair alone with the same opts
+ * (opts->inv_mass_a/b are ignored: masses come from the pairs).  A pair that
+ * fails (invalid input, zone limit, short output list) gets that status and
+ * does not stop the others.  batch_stats (host, or NULL) receives the sums
+ * over the pairs of every counter, the maxima of rounds, max_zone,
+ * max_query_path and round_max_zone, converged = 1 if all converged, and
+ * stage_ms summed over pairs (stages of different pairs overlap in time).
+ * The call waits for `stream` first (inputs written on it are complete) and
+ * returns after every pair's results are written.  Returns a negative status
+ * if the call as a whole failed (bad arguments, workers could not be
+ * created); else HFCR_OK if every pair's status is HFCR_OK, otherwise the
+ * status of the first pair whose status is not. */
+hfcr_status hfcr_resolve_batch(hfcr_ctx *ctx, hfcr_pair *pairs, int32_t npairs,
+                               const hfcr_opts *opts, hfcr_stats *batch_stats,
+                               void *stream);
+
+/* hfcr_detect for every pair of a batch, run as hfcr_resolve_batch runs its
+ * pairs (d, the inverse masses and pos_*_out are unused). */
+hfcr_status hfcr_detect_batch(hfcr_ctx *ctx, hfcr_pair *pairs, int32_t npairs,
+                              const hfcr_opts *opts, hfcr_stats *batch_stats,
+                              void *stream);
 
 /* Read or replace the context's launch schedule (hfcr_tuning).  Every
  * schedule gives identical results; only speed differs.  Returns

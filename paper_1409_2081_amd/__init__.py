@@ -6,8 +6,8 @@ library must be built (``python -m paper_1409_2081_amd.build`` or
 ``__graft_entry__.build()``); there is no fallback path, so a missing library
 or device raises.
 
-Entry points mirror include/hfcr.h: ``Context.resolve``, ``Context.detect``
-and ``Context.test_orient``.
+Entry points mirror include/hfcr.h: ``Context.resolve``, ``Context.detect``,
+``Context.resolve_batch``, ``Context.detect_batch`` and ``Context.test_orient``.
 """
 from __future__ import annotations
 
@@ -36,12 +36,14 @@ BOTH_ALTERNATE = 0
 BOTH_SIMULTANEOUS = 1
 FLAG_TIMING = 1
 MAX_ZONE = 4096
+MAX_BATCH = 65536
 STAT_ROUNDS = 64
 STAGES = 8
 STAGE_NAMES = ["setup", "refit", "traverse", "exact", "stencils", "zones", "solve", "update"]
 
 EXPORTED = ["hfcr_default_opts", "hfcr_create", "hfcr_destroy", "hfcr_last_error", "hfcr_detect",
-            "hfcr_resolve", "hfcr_test_orient", "hfcr_get_tuning", "hfcr_set_tuning"]
+            "hfcr_resolve", "hfcr_resolve_batch", "hfcr_detect_batch", "hfcr_test_orient",
+            "hfcr_get_tuning", "hfcr_set_tuning"]
 
 
 class Mesh(ctypes.Structure):
@@ -88,7 +90,7 @@ class Stats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("trav_block", ctypes.c_int32), ("trav_warm", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("batch_workers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -96,6 +98,13 @@ class Result(ctypes.Structure):
                 ("hits", ctypes.c_void_p), ("hit_cap", ctypes.c_int64),
                 ("stencils", ctypes.c_void_p), ("stencil_cap", ctypes.c_int64),
                 ("stats", ctypes.POINTER(Stats))]
+
+
+class PairDesc(ctypes.Structure):
+    """hfcr_pair: one mesh pair of a batch call."""
+    _fields_ = [("a", Mesh), ("b", Mesh), ("orientation", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("d", ctypes.c_double), ("inv_mass_a", ctypes.c_void_p), ("inv_mass_b", ctypes.c_void_p),
+                ("res", Result)]
 
 
 _LIB = None
@@ -123,6 +132,11 @@ def lib():
         L.hfcr_resolve.argtypes = [vp, ctypes.POINTER(Mesh), ctypes.POINTER(Mesh), ctypes.c_int32,
                                    ctypes.c_double, ctypes.POINTER(Opts), ctypes.POINTER(Result), vp]
         L.hfcr_resolve.restype = ctypes.c_int
+        for name in ("hfcr_resolve_batch", "hfcr_detect_batch"):
+            f = getattr(L, name)
+            f.argtypes = [vp, ctypes.POINTER(PairDesc), ctypes.c_int32, ctypes.POINTER(Opts),
+                          ctypes.POINTER(Stats), vp]
+            f.restype = ctypes.c_int
         L.hfcr_test_orient.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
         L.hfcr_test_orient.restype = ctypes.c_int
         L.hfcr_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -186,12 +200,12 @@ class Context:
         st = self._L.hfcr_get_tuning(self._h, ctypes.byref(t))
         if st != HFCR_OK:
             raise HfcrError(st, self.last_error())
-        return {"trav_block": t.trav_block, "trav_warm": t.trav_warm}
+        return {"trav_block": t.trav_block, "trav_warm": t.trav_warm, "batch_workers": t.batch_workers}
 
     def set_tuning(self, **kw) -> None:
         cur = self.get_tuning()
         cur.update(kw)
-        t = Tuning(int(cur["trav_block"]), int(cur["trav_warm"]), 0, 0)
+        t = Tuning(int(cur["trav_block"]), int(cur["trav_warm"]), int(cur["batch_workers"]), 0)
         st = self._L.hfcr_set_tuning(self._h, ctypes.byref(t))
         if st != HFCR_OK:
             raise HfcrError(st, self.last_error())
@@ -267,6 +281,74 @@ class Context:
         return {"status": st, "hits": hits[: stats.hits0], "stencils": sten[: stats.stencils0],
                 "stats": stats.to_dict()}
 
+    def _batch(self, fn, items, detect: bool, hit_cap, stencil_cap, want_lists, stream, opt_kw):
+        torch = _torch()
+        n = len(items)
+        arr = (PairDesc * max(n, 1))()
+        keep, outs = [], []
+        stats = [Stats() for _ in range(n)]
+        caps_h = hit_cap if isinstance(hit_cap, (list, tuple)) else [hit_cap] * n
+        caps_s = stencil_cap if isinstance(stencil_cap, (list, tuple)) else [stencil_cap] * n
+        dev = None
+        for i, it in enumerate(items):
+            pa, ta, pb, tb = it["pos_a"], it["tri_a"], it["pos_b"], it["tri_b"]
+            dev = pa.device
+            q = arr[i]
+            q.a, q.b = _mesh(pa, ta), _mesh(pb, tb)
+            q.orientation = int(it.get("orientation", ORIENT_B))
+            q.d = float(it.get("d", 1e-3))
+            wa, wb = it.get("inv_mass_a"), it.get("inv_mass_b")
+            q.inv_mass_a = wa.data_ptr() if wa is not None else None
+            q.inv_mass_b = wb.data_ptr() if wb is not None else None
+            out_a = None if detect else torch.empty_like(pa)
+            out_b = None if detect else torch.empty_like(pb)
+            hits = torch.empty((caps_h[i], 5), dtype=torch.int32, device=dev) if want_lists else None
+            sten = torch.empty((caps_s[i], 3), dtype=torch.int32, device=dev) if want_lists else None
+            q.res = Result(out_a.data_ptr() if out_a is not None and out_a.numel() else None,
+                           out_b.data_ptr() if out_b is not None and out_b.numel() else None,
+                           hits.data_ptr() if hits is not None else None, caps_h[i],
+                           sten.data_ptr() if sten is not None else None, caps_s[i],
+                           ctypes.pointer(stats[i]))
+            keep.append((wa, wb))
+            outs.append((out_a, out_b, hits, sten))
+        bstats = Stats()
+        o = self._opts(**opt_kw)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream if dev is not None else 0
+        st = fn(self._h, arr, n, ctypes.byref(o), ctypes.byref(bstats), ctypes.c_void_p(stream))
+        # a negative status no pair carries is a failure of the call as a whole
+        if st < 0 and all(arr[i].status != st for i in range(n)):
+            raise HfcrError(st, self.last_error())
+        if want_lists and any(arr[i].status == HFCR_E_CAPACITY for i in range(n)):
+            nh = [max(caps_h[i], stats[i].hits0) for i in range(n)]
+            ns = [max(caps_s[i], stats[i].stencils0) for i in range(n)]
+            return self._batch(fn, items, detect, nh, ns, want_lists, stream, opt_kw)
+        res = []
+        for i in range(n):
+            out_a, out_b, hits, sten = outs[i]
+            r = {"status": arr[i].status, "status_name": STATUS_NAMES.get(arr[i].status, str(arr[i].status)),
+                 "stats": stats[i].to_dict()}
+            if not detect:
+                r["pos_a"], r["pos_b"] = out_a, out_b
+            if want_lists:
+                r["hits"] = hits[: min(stats[i].hits0, caps_h[i])]
+                r["stencils"] = sten[: min(stats[i].stencils0, caps_s[i])]
+            res.append(r)
+        return {"status": st, "status_name": STATUS_NAMES.get(st, str(st)), "pairs": res,
+                "stats": bstats.to_dict(), "error": self.last_error() if st != HFCR_OK else ""}
+
+    def resolve_batch(self, items, *, hit_cap=4096, stencil_cap=4096, want_lists=True, stream=None,
+                      **opt_kw) -> dict:
+        """hfcr_resolve_batch over items: dicts with pos_a, tri_a, pos_b, tri_b and optionally
+        orientation, d, inv_mass_a, inv_mass_b.  Returns per-pair results and the batch stats."""
+        return self._batch(self._L.hfcr_resolve_batch, items, False, hit_cap, stencil_cap, want_lists,
+                           stream, opt_kw)
+
+    def detect_batch(self, items, *, hit_cap=4096, stencil_cap=4096, stream=None, **opt_kw) -> dict:
+        """hfcr_detect_batch: one DCD pass per oriented direction for every pair."""
+        return self._batch(self._L.hfcr_detect_batch, items, True, hit_cap, stencil_cap, True, stream,
+                           opt_kw)
+
     def test_orient(self, pts, tier: int, stream=None):
         """Signs of orient for pts [n,4,3] float64 (device); 2 means unsure (tiers 0 and 1)."""
         torch = _torch()
@@ -278,6 +360,13 @@ class Context:
         if st != HFCR_OK:
             raise HfcrError(st, self.last_error())
         return out
+
+
+def pair_item(pair, device="cuda") -> dict:
+    """A resolve_batch item from a meshgen.Pair."""
+    pa, ta, pb, tb = pair_tensors(pair, device)
+    return {"pos_a": pa, "tri_a": ta, "pos_b": pb, "tri_b": tb, "orientation": pair.orientation,
+            "d": pair.d}
 
 
 def pair_tensors(pair, device="cuda"):

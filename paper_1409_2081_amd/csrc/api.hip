@@ -3,10 +3,12 @@
 // status reporting.  Every arithmetic step runs in the kernels; the host
 // only sequences launches and reads back the counts that size the next step.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hfcr.h"
@@ -78,7 +80,10 @@ struct hfcr_ctx {
   std::vector<Timer> timers;
   std::vector<hipEvent_t> free_events;
   bool timing = false;
-  hfcr_tuning tune{128, 1, 0, 0};
+  hfcr_tuning tune{128, 1, 8, 0};
+  // batch calls: one context and stream per concurrent worker
+  std::vector<hfcr_ctx *> workers;
+  std::vector<hipStream_t> wstreams;
 };
 
 namespace {
@@ -629,10 +634,12 @@ hfcr_status hfcr_create(hfcr_ctx **out, int device) {
 
 void hfcr_destroy(hfcr_ctx *c) {
   if (!c) return;
+  for (hfcr_ctx *w : c->workers) hfcr_destroy(w);
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  for (hipStream_t s : c->wstreams) (void)hipStreamDestroy(s);
   DBuf *all[] = {&c->sk0, &c->sk1, &c->sv0, &c->sv1, &c->hist, &c->flags, &c->pos, &c->bsums, &c->st_keys,
                  &c->st_out_keys, &c->con, &c->parent, &c->zkeys, &c->zvals, &c->starts, &c->lambda, &c->inc_keys,
                  &c->solve_scratch, &c->ctr};
@@ -707,12 +714,13 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
     try {
       for (int r = 0; r <= o.max_rounds; ++r) {
         int act[2], nact = 0;
-        int64_t nhits = 0;
+        int64_t nhits = 0, nf = 0, ns = 0;
+        bool second_done = false;
+        const int first = (int)(((int64_t)r + o.round_offset) & 1);
         if (alternate) {
-          const int first = (int)(((int64_t)r + o.round_offset) & 1);
-          const int64_t nf = detect_dir(c, P, first, r == 0);
-          int64_t ns = 0;
-          if (r == 0 || nf == 0) ns = detect_dir(c, P, 1 - first, r == 0);
+          nf = detect_dir(c, P, first, r == 0);
+          second_done = r == 0 || nf == 0;
+          if (second_done) ns = detect_dir(c, P, 1 - first, r == 0);
           else P.hits_n[1 - first] = 0;
           if (r == 0) write_hit_outputs(c, P, res, st, truncated);
           if (nf > 0) {
@@ -739,9 +747,9 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
           break;
         }
         if (r == o.max_rounds) {
+          // residual over every oriented direction at the final positions
           residual = nhits;
-          if (alternate && nact == 1 && P.hits_n[1 - act[0]] == 0 && act[0] == (int)(((int64_t)r + o.round_offset) & 1))
-            residual += detect_dir(c, P, 1 - act[0], false);
+          if (alternate) residual = nf + (second_done ? ns : detect_dir(c, P, 1 - first, false));
           break;
         }
         const int64_t S = build_stencils(c, P, act, nact, c->st_keys);
@@ -782,6 +790,124 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// The per-pair entry point on a worker's context and stream.
+hfcr_status run_pair(hfcr_ctx *w, hipStream_t s, hfcr_pair &q, const hfcr_opts &o, bool detect, hfcr_stats *st) {
+  hfcr_opts po = o;
+  po.inv_mass_a = q.inv_mass_a;
+  po.inv_mass_b = q.inv_mass_b;
+  hfcr_result r = q.res;
+  r.stats = st;
+  if (detect) {
+    r.pos_a_out = r.pos_b_out = nullptr;
+    return hfcr_detect(w, &q.a, &q.b, q.orientation, &po, &r, s);
+  }
+  return hfcr_resolve(w, &q.a, &q.b, q.orientation, q.d, &po, &r, s);
+}
+
+void add_stats(hfcr_stats &b, const hfcr_stats &s) {
+  b.rounds = std::max(b.rounds, s.rounds);
+  b.converged = b.converged && s.converged;
+  b.residual_hits += s.residual_hits;
+  b.hits0 += s.hits0;
+  b.stencils0 += s.stencils0;
+  b.candidates += s.candidates;
+  b.exact_tests += s.exact_tests;
+  b.f32_ambiguous += s.f32_ambiguous;
+  b.max_zone = std::max(b.max_zone, s.max_zone);
+  b.rank_deficient += s.rank_deficient;
+  b.node_visits += s.node_visits;
+  b.pivoted_zones += s.pivoted_zones;
+  b.max_query_path = std::max(b.max_query_path, s.max_query_path);
+  for (int k = 0; k < HFCR_STAGES; ++k) {
+    b.stage_ms[k] += s.stage_ms[k];
+    b.stage_calls[k] += s.stage_calls[k];
+  }
+  for (int r = 0; r < HFCR_STAT_ROUNDS; ++r) {
+    b.round_hits[r] += s.round_hits[r];
+    b.round_stencils[r] += s.round_stencils[r];
+    b.round_zones[r] += s.round_zones[r];
+    b.round_max_zone[r] = std::max(b.round_max_zone[r], s.round_max_zone[r]);
+  }
+}
+
+// Batch calls: pairs are dealt dynamically to `batch_workers` host threads,
+// each driving its own context and stream, so the launches and host waits of
+// different pairs overlap on the device.  Every pair runs exactly the
+// single-pair path, so its results do not depend on the batch.
+hfcr_status run_batch(hfcr_ctx *c, hfcr_pair *pairs, int32_t n, const hfcr_opts *opts, hfcr_stats *bst,
+                      hipStream_t caller, bool detect) {
+  if (n < 0 || n > HFCR_MAX_BATCH) throw StatusError{HFCR_E_INVALID, "npairs must be in [0, HFCR_MAX_BATCH]"};
+  if (n > 0 && !pairs) throw StatusError{HFCR_E_INVALID, "pairs is NULL"};
+  hfcr_opts o;
+  hfcr_default_opts(&o);
+  if (opts) o = *opts;
+  // inputs produced on the caller's stream are complete before the workers start
+  HIP_CHECK(hipStreamSynchronize(caller));
+  const int nw = std::max(1, std::min<int>(c->tune.batch_workers, n));
+  while ((int)c->workers.size() < nw) {
+    hfcr_ctx *w = nullptr;
+    const hfcr_status st = hfcr_create(&w, c->device);
+    if (st != HFCR_OK) throw StatusError{st, "worker context creation failed"};
+    w->tune = c->tune;
+    hipStream_t ws = nullptr;
+    const hipError_t e = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      hfcr_destroy(w);
+      throw HipError{e, "hipStreamCreateWithFlags"};
+    }
+    c->workers.push_back(w);
+    c->wstreams.push_back(ws);
+  }
+  std::vector<hfcr_stats> st(n);
+  std::vector<std::string> msg(n);
+  std::atomic<int> next{0};
+  auto work = [&](int wi) {
+    hfcr_ctx *w = c->workers[wi];
+    w->tune = c->tune;
+    for (;;) {
+      const int p = next.fetch_add(1);
+      if (p >= n) break;
+      std::memset(&st[p], 0, sizeof(hfcr_stats));
+      pairs[p].status = run_pair(w, c->wstreams[wi], pairs[p], o, detect, &st[p]);
+      if (pairs[p].status < 0) msg[p] = w->err;
+      if (pairs[p].res.stats) *pairs[p].res.stats = st[p];
+    }
+  };
+  std::vector<std::thread> th;
+  for (int wi = 1; wi < nw; ++wi) th.emplace_back(work, wi);
+  work(0);
+  for (auto &t : th) t.join();
+  if (bst) {
+    std::memset(bst, 0, sizeof(*bst));
+    bst->converged = 1;
+    for (int p = 0; p < n; ++p) add_stats(*bst, st[p]);
+  }
+  for (int p = 0; p < n; ++p)
+    if (pairs[p].status != HFCR_OK) {
+      c->err = "pair " + std::to_string(p) + ": " + (msg[p].empty() ? "did not converge" : msg[p]);
+      return (hfcr_status)pairs[p].status;
+    }
+  return HFCR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hfcr_status hfcr_resolve_batch(hfcr_ctx *c, hfcr_pair *pairs, int32_t npairs, const hfcr_opts *opts,
+                               hfcr_stats *batch_stats, void *stream) {
+  return guarded(c, [&]() { return run_batch(c, pairs, npairs, opts, batch_stats, (hipStream_t)stream, false); });
+}
+
+hfcr_status hfcr_detect_batch(hfcr_ctx *c, hfcr_pair *pairs, int32_t npairs, const hfcr_opts *opts,
+                              hfcr_stats *batch_stats, void *stream) {
+  return guarded(c, [&]() { return run_batch(c, pairs, npairs, opts, batch_stats, (hipStream_t)stream, true); });
+}
+
 hfcr_status hfcr_get_tuning(const hfcr_ctx *c, hfcr_tuning *t) {
   if (!c || !t) return HFCR_E_INVALID;
   *t = c->tune;
@@ -796,6 +922,10 @@ hfcr_status hfcr_set_tuning(hfcr_ctx *c, const hfcr_tuning *t) {
   }
   if (t->trav_warm != 0 && t->trav_warm != 1) {
     c->err = "trav_warm must be 0 or 1";
+    return HFCR_E_INVALID;
+  }
+  if (t->batch_workers < 1 || t->batch_workers > 64) {
+    c->err = "batch_workers must be in [1, 64]";
     return HFCR_E_INVALID;
   }
   c->tune = *t;

@@ -548,26 +548,27 @@ void launch_refit(const MeshDev &m, hipStream_t s) {
       k_refit_chunk<false><<<nchunks, kChunk, 0, s>>>(m.leaf_tri, m.nt, m.x64, m.x32, m.nv, m.nodes,
                                                       m.leaf_parent, m.top_pos, m.root_box);
     if (nchunks > 1) {
-      static bool attr_set = false;
-      if (!attr_set) {
+      static const bool attr_set = [] {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_refit_top),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, kTopLds * (int)sizeof(int));
-        attr_set = true;
-      }
+        return true;
+      }();
+      (void)attr_set;
       const size_t bytes = (size_t)std::min<int64_t>((int64_t)nchunks * 64, m.nt) * sizeof(int);
       k_refit_top<<<1, 1024, bytes, s>>>(m.nodes, m.top_pos, m.top_list, m.top_pre, m.top_count, m.root_box);
     }
     return;
   }
   if (kRefitSingleWg && m.nt >= 2 && m.nt - 1 <= kRefitWgMaxNodes) {
-    static bool attr_set[2] = {false, false};
     const size_t bytes = (size_t)(m.nt - 1) * sizeof(int);
-    const void *fn = m.f32 ? reinterpret_cast<const void *>(&k_refit_wg<true>)
-                           : reinterpret_cast<const void *>(&k_refit_wg<false>);
-    if (!attr_set[m.f32 ? 1 : 0]) {
-      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kRefitWgMaxNodes * (int)sizeof(int));
-      attr_set[m.f32 ? 1 : 0] = true;
-    }
+    static const bool attr_set = [] {
+      for (const void *fn : {reinterpret_cast<const void *>(&k_refit_wg<true>),
+                             reinterpret_cast<const void *>(&k_refit_wg<false>)})
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kRefitWgMaxNodes * (int)sizeof(int));
+      return true;
+    }();
+    (void)attr_set;
     if (m.f32)
       k_refit_wg<true><<<1, kRefitBlock, bytes, s>>>(m.leaf_tri, m.nt, m.x64, m.x32, m.nv, m.nodes, m.leaf_parent,
                                                      m.root_box);

@@ -799,12 +799,13 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
 template <bool MAT_LDS, bool VEC_LDS>
 static void launch_class(const SolveArgs &a, int kmin, int kcap, int grid, hipStream_t s) {
   const size_t bytes = MAT_LDS ? zone_lds_bytes(true, kcap) : (VEC_LDS ? zone_vec_bytes(kcap) : 0) + 4 * 16 + 64;
-  static bool attr_set = false;  // the attribute is per function
-  if (!attr_set) {
+  // the attribute is per function; set once (thread-safe static initialisation)
+  static const bool attr_set = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve<MAT_LDS, VEC_LDS>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
+    return true;
+  }();
+  (void)attr_set;
   k_solve<MAT_LDS, VEC_LDS><<<grid, kSolveBlock, bytes, s>>>(a, kmin, kcap);
 }
 

@@ -20,6 +20,7 @@ STRUCTS = {
     "hfcr_stats": hf.Stats,
     "hfcr_result": hf.Result,
     "hfcr_tuning": hf.Tuning,
+    "hfcr_pair": hf.PairDesc,
 }
 
 
