@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "E-F tests/sec, resolved mesh pairs/sec; p50/p99 resolve latency (1 MI355X)"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20
 
 
 def traverse_bytes(pair, ne_a: int, ne_b: int, launches_dir: dict) -> float:
@@ -48,6 +49,25 @@ def traverse_bytes(pair, ne_a: int, ne_b: int, launches_dir: dict) -> float:
         1: 16 * ne_b + 12 * nv_b + 64 * (nt_a - 1) + 16 * nt_a + 12 * nv_a,
     }
     return sum(per[d] * n for d, n in launches_dir.items())
+
+
+def measured_traffic():
+    """HBM bytes per traversal launch from the committed counter record, or None.
+
+    The record (profiles/k_traverse_hbm_counters.json) holds FETCH_SIZE and
+    WRITE_SIZE per dispatch, scaled by what the same counters read for a
+    256 MiB device copy, and the SHA-256 of the traversal sources it was
+    taken with; a changed kernel makes the figure stale, and then it is None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_traverse_hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def progress(msg: str) -> None:
@@ -74,12 +94,18 @@ def bench_batch(ctx, args) -> dict:
     pairs = meshgen.pair_set(seed=4, n=args.batch_pairs)
     items = [hf.pair_item(p, "cuda:0") for p in pairs]
     plain = [hf.pair_item(dataclasses.replace(p, dtype=meshgen.F64, tier=1).cast(), "cuda:0") for p in pairs]
-    kw = dict(max_rounds=args.rounds, want_lists=False)
-    progress("batch: warm-up call")
+    kw = dict(max_rounds=args.batch_rounds, want_lists=False)
+    # warm-up in chunks (creates the workers and shows where the time goes)
     t = time.perf_counter()
-    ctx.resolve_batch(items, tier=0, **kw)  # warm-up (creates the workers)
+    for c0 in range(0, len(items), 16):
+        tc = time.perf_counter()
+        w = ctx.resolve_batch(items[c0:c0 + 16], tier=0, timing=True, **kw)
+        sm = w["stats"]["stage_ms"]
+        progress(f"batch warm-up: pairs {c0}..{c0 + 15}: {time.perf_counter() - tc:.2f} s, "
+                 f"max zone {w['stats']['max_zone']}, rounds {w['stats']['rounds']}, "
+                 f"solve {sm['solve']:.0f} ms, traverse {sm['traverse']:.0f} ms (summed over pairs)")
     torch.cuda.synchronize()
-    progress(f"batch: warm-up call took {time.perf_counter() - t:.2f} s")
+    progress(f"batch: warm-up took {time.perf_counter() - t:.2f} s")
     t = time.perf_counter()
     for k in range(args.batch_steps):
         b = ctx.resolve_batch(items, tier=0, timing=True, **kw)
@@ -107,7 +133,7 @@ def bench_batch(ctx, args) -> dict:
         "workload": f"{n} mixed pairs (half sphere-sheet, half linked tori), triangles per mesh log-uniform "
                     f"in [500, 50000], depth U[0.1, 0.4], random rigid motions, seed 4; "
                     f"{sum(len(p.tri_a) + len(p.tri_b) for p in pairs)} triangles in all",
-        "max_rounds": args.rounds, "workers": ctx.get_tuning()["batch_workers"],
+        "max_rounds": args.batch_rounds, "workers": ctx.get_tuning()["batch_workers"],
         "batched_pairs_per_s": n / tb, "batched_ms_per_call": 1e3 * tb,
         "plain_f64_pairs_per_s": n / tp, "plain_f64_ms_total": 1e3 * tp,
         "speedup_vs_plain": tp / tb,
@@ -133,6 +159,10 @@ def main():
     ap.add_argument("--batch-pairs", type=int, default=256,
                     help="pairs of the mixed pair set in the batched measurement (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=1)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run 3 linked-tori steps and a 256 MiB device copy (for HBM counter passes), then exit")
+    ap.add_argument("--batch-rounds", type=int, default=4,
+                    help="response-round budget per pair in the batched and plain measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -149,6 +179,17 @@ def main():
     ctx = hf.Context(0)
     tens = hf.pair_tensors(pair, "cuda:0")
     kw = dict(tier=pair.tier, max_rounds=args.rounds, want_lists=False)
+    if args.pmc_probe:
+        # the counters of the copy calibrate FETCH_SIZE / WRITE_SIZE against known bytes
+        for _ in range(3):
+            ctx.resolve(*tens, pair.orientation, pair.d, **kw)
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES}))
+        return
 
     progress("linked tori: warm-up")
     for _ in range(args.warmup):
@@ -194,7 +235,7 @@ def main():
     roofline = {
         "kernel": "k_traverse<true,true> (BVH traversal + float32-filtered narrow phase)",
         "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
         "avg_launch_ms": trav_avg_ms, "algorithmic_bytes_per_launch": trav_bytes_per_launch,
         "launches_per_step": launches,
     }
