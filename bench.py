@@ -147,6 +147,88 @@ def bench_batch(ctx, args) -> dict:
     }
 
 
+def bench_serving(args) -> dict:
+    """Open-loop serving: Poisson arrivals of resolve requests of uneven sizes.
+
+    A pool of 64 pairs (half sphere-sheet, half linked tori, triangles per
+    mesh log-uniform in [1k, 200k], seed 5) is made resident; request i
+    resolves pool[i % 64] (outputs fresh per request).  The saturated
+    closed-loop throughput is measured first (every request submitted at
+    once); the open loop then offers 0.7 of it with exponential
+    inter-arrival times (seed 5).  Latency = submission to completion.
+    """
+    import threading
+
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_1409_2081_amd as hf
+
+    progress("serving: generating the request pool")
+    pool = meshgen.pair_set(seed=5, n=64, f_lo=1000.0, f_hi=200000.0)
+    items = [hf.pair_item(p, "cuda:0") for p in pool]
+    torch.cuda.synchronize()
+    kw = dict(max_rounds=args.serve_rounds, tier=0, want_lists=False)
+    srv = hf.Server(0, slots=args.serve_slots, pool_bytes=args.serve_pool_mib << 20)
+    try:
+        # warm-up: every pool pair once (workspaces grow to their size)
+        for t in [srv.submit(it, **kw) for it in items]:
+            srv.wait(t)
+        progress("serving: warm-up done")
+        n_sat = min(args.serve_requests, 256)
+        t0 = time.perf_counter()
+        ts = [srv.submit(items[i % len(items)], **kw) for i in range(n_sat)]
+        for t in ts:
+            srv.wait(t)
+        sat = n_sat / (time.perf_counter() - t0)
+        rate = 0.7 * sat
+        progress(f"serving: saturated {sat:.1f} requests/s; offering {rate:.1f}/s")
+        rng = np.random.default_rng(5)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, args.serve_requests))
+        tickets, lat, status = [], [], []
+        done = threading.Event()
+
+        def collect():
+            k = 0
+            while k < args.serve_requests:
+                if k >= len(tickets):
+                    time.sleep(1e-4)
+                    continue
+                r = srv.wait(tickets[k])
+                lat.append(r["latency_ms"])
+                status.append(r["status"])
+                k += 1
+                if k % 100 == 0:
+                    progress(f"serving: {k}/{args.serve_requests} requests done")
+            done.set()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for i, a in enumerate(arrivals):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            tickets.append(srv.submit(items[i % len(items)], **kw))
+        th.join()
+        wall = time.perf_counter() - t0
+    finally:
+        srv.close()
+    lat_s = sorted(lat)
+    pick = lambda q: lat_s[min(len(lat_s) - 1, int(round(q * (len(lat_s) - 1))))]
+    return {
+        "workload": f"Poisson arrivals of {args.serve_requests} resolve requests over a pool of 64 pairs "
+                    "(sphere-sheet / linked tori, triangles per mesh log-uniform in [1k, 200k], seed 5), "
+                    f"max_rounds {args.serve_rounds}, float32-filtered",
+        "slots": args.serve_slots, "pool_bytes": args.serve_pool_mib << 20,
+        "saturated_requests_per_s": sat, "offered_requests_per_s": rate,
+        "completed_requests_per_s": len(lat) / wall, "p50_ms": pick(0.5), "p99_ms": pick(0.99),
+        "mean_ms": float(np.mean(lat)), "statuses": {hf.STATUS_NAMES[k]: status.count(k) for k in set(status)},
+        "pool_triangles": sum(len(p.tri_a) + len(p.tri_b) for p in pool),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +241,11 @@ def main():
     ap.add_argument("--batch-pairs", type=int, default=256,
                     help="pairs of the mixed pair set in the batched measurement (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=1)
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests of the open-loop serving measurement (0: skip it)")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-pool-mib", type=int, default=1024)
+    ap.add_argument("--serve-rounds", type=int, default=4)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run 3 linked-tori steps and a 256 MiB device copy (for HBM counter passes), then exit")
     ap.add_argument("--batch-rounds", type=int, default=4,
@@ -263,6 +350,8 @@ def main():
     progress(f"linked tori: {args.steps} steps in {wall:.2f} s")
     if args.batch_pairs > 0:
         out["batch"] = bench_batch(ctx, args)
+    if args.serve_requests > 0:
+        out["serving"] = bench_serving(args)
 
     if not args.no_cpu:
         import oracle

@@ -64,14 +64,17 @@ extern "C" {
 typedef enum {
   HFCR_OK = 0,
   HFCR_NOT_CONVERGED = 1, /* max_rounds responses made, hits remain        */
+  HFCR_PENDING = 2,       /* hfcr_server_wait: not finished within the wait  */
   HFCR_E_INVALID = -1,    /* bad argument, index out of range, non-finite
                              or out-of-domain coordinate                    */
   HFCR_E_CAPACITY = -2,   /* a caller output list was too short; stats hold
                              the required counts, positions are valid       */
   HFCR_E_OOM = -3,        /* device allocation failed                       */
   HFCR_E_DEVICE = -4,     /* a HIP runtime call failed                      */
-  HFCR_E_ZONE_LIMIT = -5  /* an impact zone exceeded HFCR_MAX_ZONE stencils;
+  HFCR_E_ZONE_LIMIT = -5, /* an impact zone exceeded HFCR_MAX_ZONE stencils;
                              positions hold the state before that round     */
+  HFCR_E_REJECTED = -6    /* a request larger than the server's memory
+                             budget, or a server that is shutting down     */
 } hfcr_status;
 
 typedef enum { HFCR_F32 = 0, HFCR_F64 = 1 } hfcr_dtype;
@@ -170,7 +173,7 @@ typedef struct {
   int32_t trav_block;    /* traversal workgroup size: 64, 128 or 256 (128)  */
   int32_t trav_warm;     /* 1: warm the L2 with the face BVH first (1)      */
   int32_t batch_workers; /* pairs in flight at once in the batch calls,
-                            each on its own stream, 1..64 (8)               */
+                            each on its own stream, 1..64 (12)              */
   int32_t reserved;
 } hfcr_tuning;
 
@@ -246,6 +249,58 @@ hfcr_status hfcr_resolve_batch(hfcr_ctx *ctx, hfcr_pair *pairs, int32_t npairs,
 hfcr_status hfcr_detect_batch(hfcr_ctx *ctx, hfcr_pair *pairs, int32_t npairs,
                               const hfcr_opts *opts, hfcr_stats *batch_stats,
                               void *stream);
+
+/* ------------------------------------------------------------ serving
+ * A request server for a stream of independent resolves of uneven sizes.
+ * Requests are admitted in arrival order while a slot is free and the sum
+ * of the admitted requests' estimated device footprints stays within
+ * pool_bytes; each slot is a worker with its own context (its device
+ * workspace stays allocated between requests) and its own stream, so the
+ * work of admitted requests overlaps on the GPU.  Every request runs the
+ * single-pair path of hfcr_resolve, so its results are bit-identical to a
+ * call of hfcr_resolve on the same pair alone.
+ *
+ * Footprint estimate of a request (bytes): 512 per vertex and 1024 per
+ * triangle of the two meshes, plus 1 MiB; it bounds the workspace a
+ * resolve of that pair allocates, with a zone-solver slot budget sized for
+ * the common case.  The caller's own input and output buffers are not
+ * counted. */
+typedef struct hfcr_server hfcr_server;
+
+typedef struct {
+  int32_t slots;       /* requests on the device at once, 1..64 (default 8)   */
+  int32_t reserved;
+  int64_t pool_bytes;  /* budget for the admitted footprints; 0 = unlimited */
+} hfcr_server_cfg;
+
+/* Create a server on HIP device `device` (cfg NULL = defaults). */
+hfcr_status hfcr_server_create(hfcr_server **out, int device, const hfcr_server_cfg *cfg);
+
+/* Stop admitting, finish every admitted and queued request, release the
+ * workers. */
+void hfcr_server_destroy(hfcr_server *srv);
+
+/* Queue one resolve (the fields of *pair as for hfcr_resolve_batch, opts as
+ * for hfcr_resolve; opts->inv_mass_a/b are ignored).  Returns at once with
+ * a ticket.  *pair and every buffer it names must stay valid until
+ * hfcr_server_wait has returned a final status for the ticket; the result is
+ * written to pair->status and pair->res.  Inputs must be complete on the
+ * device (synchronised) before the call.  Returns HFCR_E_REJECTED for a
+ * request whose footprint exceeds pool_bytes. */
+hfcr_status hfcr_server_submit(hfcr_server *srv, hfcr_pair *pair, const hfcr_opts *opts,
+                               uint64_t *ticket);
+
+/* Wait up to timeout_us microseconds (< 0: without limit) for a ticket.
+ * Returns the request's status once it has finished (then the ticket is
+ * released), or HFCR_PENDING.  *latency_ms (may be NULL) receives the time
+ * from submission to completion.  An unknown ticket gives HFCR_E_INVALID. */
+hfcr_status hfcr_server_wait(hfcr_server *srv, uint64_t ticket, int64_t timeout_us,
+                             double *latency_ms);
+
+/* Counters of a server: requests queued, running, completed, and the
+ * footprint currently admitted (bytes); any pointer may be NULL. */
+void hfcr_server_counts(const hfcr_server *srv, int64_t *queued, int64_t *running,
+                        int64_t *completed, int64_t *admitted_bytes);
 
 /* Read or replace the context's launch schedule (hfcr_tuning).  Every
  * schedule gives identical results; only speed differs.  Returns

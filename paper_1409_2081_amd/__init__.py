@@ -19,13 +19,15 @@ LIB_PATH = os.path.join(HERE, "libhfcr.so")
 
 HFCR_OK = 0
 HFCR_NOT_CONVERGED = 1
+HFCR_PENDING = 2
 HFCR_E_INVALID = -1
 HFCR_E_CAPACITY = -2
 HFCR_E_OOM = -3
 HFCR_E_DEVICE = -4
 HFCR_E_ZONE_LIMIT = -5
-STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_OOM",
-                -4: "E_DEVICE", -5: "E_ZONE_LIMIT"}
+HFCR_E_REJECTED = -6
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_OOM",
+                -4: "E_DEVICE", -5: "E_ZONE_LIMIT", -6: "E_REJECTED"}
 
 HFCR_F32 = 0
 HFCR_F64 = 1
@@ -43,7 +45,8 @@ STAGE_NAMES = ["setup", "refit", "traverse", "exact", "stencils", "zones", "solv
 
 EXPORTED = ["hfcr_default_opts", "hfcr_create", "hfcr_destroy", "hfcr_last_error", "hfcr_detect",
             "hfcr_resolve", "hfcr_resolve_batch", "hfcr_detect_batch", "hfcr_test_orient",
-            "hfcr_get_tuning", "hfcr_set_tuning"]
+            "hfcr_get_tuning", "hfcr_set_tuning", "hfcr_server_create", "hfcr_server_destroy",
+            "hfcr_server_submit", "hfcr_server_wait", "hfcr_server_counts"]
 
 
 class Mesh(ctypes.Structure):
@@ -107,6 +110,10 @@ class PairDesc(ctypes.Structure):
                 ("res", Result)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pool_bytes", ctypes.c_int64)]
+
+
 _LIB = None
 
 
@@ -137,6 +144,18 @@ def lib():
             f.argtypes = [vp, ctypes.POINTER(PairDesc), ctypes.c_int32, ctypes.POINTER(Opts),
                           ctypes.POINTER(Stats), vp]
             f.restype = ctypes.c_int
+        L.hfcr_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ServerCfg)]
+        L.hfcr_server_create.restype = ctypes.c_int
+        L.hfcr_server_destroy.argtypes = [vp]
+        L.hfcr_server_destroy.restype = None
+        L.hfcr_server_submit.argtypes = [vp, ctypes.POINTER(PairDesc), ctypes.POINTER(Opts),
+                                         ctypes.POINTER(ctypes.c_uint64)]
+        L.hfcr_server_submit.restype = ctypes.c_int
+        L.hfcr_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]
+        L.hfcr_server_wait.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.hfcr_server_counts.argtypes = [vp, i64p, i64p, i64p, i64p]
+        L.hfcr_server_counts.restype = None
         L.hfcr_test_orient.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
         L.hfcr_test_orient.restype = ctypes.c_int
         L.hfcr_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -360,6 +379,87 @@ class Context:
         if st != HFCR_OK:
             raise HfcrError(st, self.last_error())
         return out
+
+
+class Server:
+    """hfcr_server_*: a request loop admitting resolves by slots and an HBM footprint budget."""
+
+    def __init__(self, device: int = 0, slots: int = 8, pool_bytes: int = 0):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        cfg = ServerCfg(int(slots), 0, int(pool_bytes))
+        st = self._L.hfcr_server_create(ctypes.byref(h), int(device), ctypes.byref(cfg))
+        if st != HFCR_OK:
+            raise HfcrError(st, "hfcr_server_create failed")
+        self._h = h
+        self._live = {}  # ticket -> (descriptor, tensors, stats) kept alive until waited
+
+    def submit(self, item: dict, *, hit_cap=4096, stencil_cap=4096, want_lists=True, **opt_kw) -> int:
+        """Queue one resolve (an item as for Context.resolve_batch); returns the ticket."""
+        torch = _torch()
+        pa, ta, pb, tb = item["pos_a"], item["tri_a"], item["pos_b"], item["tri_b"]
+        q = PairDesc()
+        q.a, q.b = _mesh(pa, ta), _mesh(pb, tb)
+        q.orientation = int(item.get("orientation", ORIENT_B))
+        q.d = float(item.get("d", 1e-3))
+        wa, wb = item.get("inv_mass_a"), item.get("inv_mass_b")
+        q.inv_mass_a = wa.data_ptr() if wa is not None else None
+        q.inv_mass_b = wb.data_ptr() if wb is not None else None
+        out_a, out_b = torch.empty_like(pa), torch.empty_like(pb)
+        hits = torch.empty((hit_cap, 5), dtype=torch.int32, device=pa.device) if want_lists else None
+        sten = torch.empty((stencil_cap, 3), dtype=torch.int32, device=pa.device) if want_lists else None
+        stats = Stats()
+        q.res = Result(out_a.data_ptr() if out_a.numel() else None, out_b.data_ptr() if out_b.numel() else None,
+                       hits.data_ptr() if hits is not None else None, hit_cap,
+                       sten.data_ptr() if sten is not None else None, stencil_cap, ctypes.pointer(stats))
+        o = Context._opts(**opt_kw)
+        torch.cuda.synchronize(pa.device)  # inputs (and the fresh outputs) are complete on the device
+        t = ctypes.c_uint64()
+        st = self._L.hfcr_server_submit(self._h, ctypes.byref(q), ctypes.byref(o), ctypes.byref(t))
+        if st != HFCR_OK:
+            raise HfcrError(st, "request rejected" if st == HFCR_E_REJECTED else "submit failed")
+        self._live[t.value] = (q, o, item, out_a, out_b, hits, sten, stats, hit_cap, stencil_cap)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """The request's result dict, or None if it is still pending after timeout_us."""
+        lat = ctypes.c_double()
+        st = self._L.hfcr_server_wait(self._h, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(lat))
+        if st == HFCR_PENDING:
+            return None
+        if st == HFCR_E_INVALID and ticket not in self._live:
+            raise HfcrError(st, "unknown ticket")
+        q, o, item, out_a, out_b, hits, sten, stats, hcap, scap = self._live.pop(ticket)
+        r = {"status": st, "status_name": STATUS_NAMES.get(st, str(st)), "latency_ms": lat.value,
+             "pos_a": out_a, "pos_b": out_b, "stats": stats.to_dict()}
+        if hits is not None:
+            r["hits"] = hits[: min(stats.hits0, hcap)]
+            r["stencils"] = sten[: min(stats.stencils0, scap)]
+        return r
+
+    def counts(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(4)]
+        self._L.hfcr_server_counts(self._h, *[ctypes.byref(x) for x in v])
+        return dict(zip(("queued", "running", "completed", "admitted_bytes"), [x.value for x in v]))
+
+    @staticmethod
+    def footprint(item: dict) -> int:
+        """The server's device-footprint estimate of a request (bytes)."""
+        nv = item["pos_a"].shape[0] + item["pos_b"].shape[0]
+        nt = item["tri_a"].shape[0] + item["tri_b"].shape[0]
+        return 512 * nv + 1024 * nt + (1 << 20)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.hfcr_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pair_item(pair, device="cuda") -> dict:

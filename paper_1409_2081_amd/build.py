@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhfcr.so")
-SOURCES = ["sort.hip", "bvh.hip", "dcd.hip", "response.hip", "api.hip"]
+SOURCES = ["sort.hip", "bvh.hip", "dcd.hip", "response.hip", "api.hip", "server.hip"]
 ARCH = os.environ.get("HFCR_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -80,7 +80,7 @@ struct hfcr_ctx {
   std::vector<Timer> timers;
   std::vector<hipEvent_t> free_events;
   bool timing = false;
-  hfcr_tuning tune{128, 1, 8, 0};
+  hfcr_tuning tune{128, 1, 12, 0};
   // batch calls: one context and stream per concurrent worker
   std::vector<hfcr_ctx *> workers;
   std::vector<hipStream_t> wstreams;

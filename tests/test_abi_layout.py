@@ -21,6 +21,7 @@ STRUCTS = {
     "hfcr_result": hf.Result,
     "hfcr_tuning": hf.Tuning,
     "hfcr_pair": hf.PairDesc,
+    "hfcr_server_cfg": hf.ServerCfg,
 }
 
 

@@ -89,7 +89,7 @@ def test_batch_equals_alone_mixed(hfcr_ctx, workers):
             _check_same(_alone(hfcr_ctx, it, **opt), got, name)
         _sums(b["stats"], b["pairs"])
         assert any(p["stats"]["rounds"] > 0 for p in b["pairs"])
-    hfcr_ctx.set_tuning(batch_workers=8)
+    hfcr_ctx.set_tuning(batch_workers=12)
 
 
 def test_batch_equals_alone_pair_set_full_size(hfcr_ctx):
