@@ -331,9 +331,157 @@ def pair_set(seed: int = 4, n: int = 256, f_lo: float = 500.0, f_hi: float = 500
     return pairs
 
 
+# ------------------------------------------------------------ capsule body
+# 12 capsules (segment end points and radius, metres, z up): torso, pelvis
+# (two spheres), neck, head, upper arms, forearms, thighs, shins.
+CAPSULES = [
+    ((0.0, 0.0, 0.95), (0.0, 0.0, 1.35), 0.16),
+    ((0.09, 0.0, 0.92), (0.09, 0.0, 0.92), 0.14),
+    ((-0.09, 0.0, 0.92), (-0.09, 0.0, 0.92), 0.14),
+    ((0.0, 0.0, 1.38), (0.0, 0.0, 1.50), 0.06),
+    ((0.0, 0.0, 1.58), (0.0, 0.0, 1.66), 0.11),
+    ((0.20, 0.0, 1.36), (0.45, 0.0, 1.12), 0.055),
+    ((-0.20, 0.0, 1.36), (-0.45, 0.0, 1.12), 0.055),
+    ((0.45, 0.0, 1.12), (0.62, 0.0, 0.90), 0.045),
+    ((-0.45, 0.0, 1.12), (-0.62, 0.0, 0.90), 0.045),
+    ((0.10, 0.0, 0.88), (0.12, 0.0, 0.48), 0.085),
+    ((-0.10, 0.0, 0.88), (-0.12, 0.0, 0.48), 0.085),
+    ((0.12, 0.0, 0.48), (0.12, 0.0, 0.08), 0.06),
+    ((-0.12, 0.0, 0.48), (-0.12, 0.0, 0.08), 0.06),
+]
+
+
+def capsule_sdf(p: np.ndarray) -> np.ndarray:
+    """Signed distance to the union of CAPSULES at points p [n, 3] (negative inside)."""
+    d = np.full(len(p), np.inf)
+    for a, b, r in CAPSULES:
+        a, b = np.asarray(a), np.asarray(b)
+        ab = b - a
+        L2 = float(ab @ ab)
+        t = np.zeros(len(p)) if L2 == 0.0 else np.clip((p - a) @ ab / L2, 0.0, 1.0)
+        d = np.minimum(d, np.linalg.norm(p - (a + t[:, None] * ab), axis=1) - r)
+    return d
+
+
+# Six tetrahedra per cube, all sharing the cube diagonal 0-7 (corner c = x + 2y + 4z);
+# neighbouring cubes split their common faces the same way, so the surface is closed.
+_KUHN = np.array([[0, 1, 3, 7], [0, 1, 5, 7], [0, 2, 3, 7], [0, 2, 6, 7], [0, 4, 5, 7], [0, 4, 6, 7]])
+
+
+def marching_tetrahedra(sdf, lo, h: float, shape, level: float = 0.0):
+    """Closed triangle mesh of {sdf = level} on the grid lo + h*(i, j, k), i < shape[0] ...
+
+    ``sdf`` maps points [n, 3] to values.  Only cubes whose corner values
+    straddle the level are split.  Crossing points are linear interpolants
+    along tetrahedron edges (shared between neighbours by the edge's grid
+    end points); triangles are wound counter-clockwise seen from outside
+    (the side where sdf > level).
+    """
+    nx, ny, nz = shape
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    pts = np.stack([ii, jj, kk], -1).reshape(-1, 3) * h + np.asarray(lo)
+    val = sdf(pts).reshape(nx, ny, nz) - level
+    val[val == 0.0] = 1e-12  # no grid node exactly on the surface
+    node = np.arange(nx * ny * nz).reshape(nx, ny, nz)
+    c = node[:-1, :-1, :-1].ravel()
+    corner_off = np.array([0, ny * nz, nz, ny * nz + nz, 1, ny * nz + 1, nz + 1, ny * nz + nz + 1])  # c = x+2y+4z
+    corners = c[:, None] + corner_off[None, :]
+    v = val.ravel()[corners]
+    keep = (v.min(1) < 0) & (v.max(1) > 0)
+    corners = corners[keep]
+    tets = corners[:, _KUHN].reshape(-1, 4)
+    tv = val.ravel()[tets]
+    inside = tv < 0
+    n_in = inside.sum(1)
+    tris, ref = [], []
+
+    def cross(u, w):  # crossing point id on grid edge (u, w)
+        return np.minimum(u, w).astype(np.int64) * (nx * ny * nz) + np.maximum(u, w)
+
+    for k in (1, 3):  # one corner separated: one triangle
+        sel = n_in == k
+        t, iv = tets[sel], inside[sel]
+        lone = iv if k == 1 else ~iv
+        a = t[lone]
+        o = t[~lone].reshape(-1, 3)
+        tris.append(np.stack([cross(a, o[:, 0]), cross(a, o[:, 1]), cross(a, o[:, 2])], 1))
+        ref.append(np.stack([a, o[:, 0]], 1) if k == 1 else np.stack([o[:, 0], a], 1))
+    sel = n_in == 2  # two and two: a quad, two triangles
+    t, iv = tets[sel], inside[sel]
+    i_ = t[iv].reshape(-1, 2)
+    o_ = t[~iv].reshape(-1, 2)
+    q = [cross(i_[:, 0], o_[:, 0]), cross(i_[:, 0], o_[:, 1]), cross(i_[:, 1], o_[:, 1]), cross(i_[:, 1], o_[:, 0])]
+    tris += [np.stack([q[0], q[1], q[2]], 1), np.stack([q[0], q[2], q[3]], 1)]
+    ref += [np.stack([i_[:, 0], o_[:, 0]], 1)] * 2
+    tri_keys = np.concatenate(tris)
+    ref = np.concatenate(ref)  # (an inside node, an outside node) of each triangle's tetrahedron
+    keys, tri = np.unique(tri_keys.ravel(), return_inverse=True)
+    tri = tri.reshape(-1, 3)
+    u, w = keys // (nx * ny * nz), keys % (nx * ny * nz)
+    fu, fw = val.ravel()[u], val.ravel()[w]
+    s_ = fu / (fu - fw)
+    pos = pts[u] + s_[:, None] * (pts[w] - pts[u])
+    # wind counter-clockwise seen from outside
+    n = np.cross(pos[tri[:, 1]] - pos[tri[:, 0]], pos[tri[:, 2]] - pos[tri[:, 0]])
+    flip = np.einsum("ij,ij->i", n, pts[ref[:, 1]] - pts[ref[:, 0]]) < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    return pos, tri.astype(np.int32)
+
+
+def capsule_surface(level: float, h: float):
+    """Marching-tetrahedra mesh of the capsule body's level set at grid spacing h."""
+    lo = np.array([-0.75, -0.25, -0.02]) - level
+    hi = np.array([0.75, 0.25, 1.80]) + level
+    shape = tuple(int(x) for x in np.ceil((hi - lo) / h) + 1)
+    return marching_tetrahedra(capsule_sdf, lo, h, shape, level)
+
+
+def _sized_surface(level: float, target: int, h0: float):
+    """capsule_surface with the grid spacing tuned to target +- 5 % triangles."""
+    h = h0
+    for _ in range(12):
+        pos, tri = capsule_surface(level, h)
+        if abs(len(tri) - target) <= 0.05 * target:
+            return pos, tri
+        h *= math.sqrt(len(tri) / target)
+    return pos, tri
+
+
+def vertex_normals(pos: np.ndarray, tri: np.ndarray) -> np.ndarray:
+    """Area-weighted unit vertex normals."""
+    fn = np.cross(pos[tri[:, 1]] - pos[tri[:, 0]], pos[tri[:, 2]] - pos[tri[:, 0]])
+    vn = np.zeros_like(pos)
+    for k in range(3):
+        np.add.at(vn, tri[:, k], fn)
+    return vn / np.maximum(np.linalg.norm(vn, axis=1, keepdims=True), 1e-300)
+
+
+def body_garment(seed: int = 3, body_tris: int = 200000, cloth_tris: int = 100000, offset: float = 0.01,
+                 frac: float = 0.05, push: float = 0.03, dtype: str = F32, tier: int = 0) -> Pair:
+    """Closed oriented capsule body (mesh B) inside a cloth shell (mesh A) pushed into it.
+
+    The body is the zero level set of the union of 12 capsules, the cloth the
+    level set at `offset`, both by marching tetrahedra with grid spacings
+    tuned to the triangle counts (+- 5 %).  A fraction `frac` of the cloth
+    vertices (chosen with default_rng(seed)) move along minus their
+    area-weighted normal by U[0, push]; those moved farther than `offset`
+    penetrate the body.
+    """
+    rng = np.random.default_rng(seed)
+    pb, tb = _sized_surface(0.0, body_tris, 0.0097 * math.sqrt(200000.0 / body_tris))
+    pa, ta = _sized_surface(offset, cloth_tris, 0.0145 * math.sqrt(100000.0 / cloth_tris))
+    n = vertex_normals(pa, ta)
+    pick = rng.choice(len(pa), size=int(round(frac * len(pa))), replace=False)
+    pa = pa.copy()
+    pa[pick] -= rng.uniform(0.0, push, len(pick))[:, None] * n[pick]
+    return Pair("body_garment", pa, ta, pb, tb, ORIENT_B, 1e-3, dtype, tier).cast()
+
+
 def workload(name: str, **kw) -> Pair:
     if name == "sphere_sheet":
         return sphere_sheet(**kw)
     if name == "linked_tori":
         return linked_tori(**kw)
+    if name == "body_garment":
+        return body_garment(**kw)
     raise KeyError(name)

@@ -43,3 +43,20 @@ def test_sized_primitives_hit_their_targets():
             assert _closed_and_outward(pos, tri)
         pos, tri = meshgen.sheet_f(target, 2.5, 0.3)
         assert abs(len(tri) - target) <= 0.05 * target
+
+
+def test_body_garment_is_closed_oriented_and_penetrating():
+    p = meshgen.body_garment(body_tris=20000, cloth_tris=10000)
+    assert abs(len(p.tri_b) - 20000) <= 1000 and abs(len(p.tri_a) - 10000) <= 500
+    assert p.orientation == meshgen.ORIENT_B and p.pos_a.dtype == np.float32
+    assert _closed_and_outward(p.pos_b.astype(float), p.tri_b)
+    assert _closed_and_outward(p.pos_a.astype(float), p.tri_a)
+    # the body surface sits on the capsules' zero level (within the linear
+    # interpolation error of a ~3 cm grid), the cloth near 0.01 outside
+    db = meshgen.capsule_sdf(p.pos_b.astype(float))
+    assert np.abs(db).max() < 0.02 and np.median(np.abs(db)) < 2e-3
+    da = meshgen.capsule_sdf(p.pos_a.astype(float))
+    inside = (da < 0).sum()
+    moved = int(round(0.05 * len(p.pos_a)))
+    # displacements U[0, 0.03] against a 0.01 offset: about two thirds end inside
+    assert 0.5 * moved < inside < 0.8 * moved
