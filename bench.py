@@ -166,7 +166,11 @@ def bench_serving(args) -> dict:
     import paper_1409_2081_amd as hf
 
     progress("serving: generating the request pool")
-    pool = meshgen.pair_set(seed=5, n=64, f_lo=1000.0, f_hi=200000.0)
+    pool = meshgen.pair_set(seed=5, n=56, f_lo=1000.0, f_hi=200000.0)
+    rng = np.random.default_rng(5)
+    for k in range(8):  # body-in-garment pairs, body triangles log-uniform in [2k, 200k]
+        fb = float(np.exp(rng.uniform(np.log(2000.0), np.log(200000.0))))
+        pool.append(meshgen.body_garment(seed=50 + k, body_tris=int(fb), cloth_tris=int(fb / 2)))
     items = [hf.pair_item(p, "cuda:0") for p in pool]
     torch.cuda.synchronize()
     kw = dict(max_rounds=args.serve_rounds, tier=0, want_lists=False)
@@ -219,13 +223,51 @@ def bench_serving(args) -> dict:
     pick = lambda q: lat_s[min(len(lat_s) - 1, int(round(q * (len(lat_s) - 1))))]
     return {
         "workload": f"Poisson arrivals of {args.serve_requests} resolve requests over a pool of 64 pairs "
-                    "(sphere-sheet / linked tori, triangles per mesh log-uniform in [1k, 200k], seed 5), "
+                    "(56 sphere-sheet / linked tori with triangles per mesh log-uniform in [1k, 200k], seed 5; "
+                    "8 body-in-garment pairs with 2k-200k body triangles), "
                     f"max_rounds {args.serve_rounds}, float32-filtered",
         "slots": args.serve_slots, "pool_bytes": args.serve_pool_mib << 20,
         "saturated_requests_per_s": sat, "offered_requests_per_s": rate,
         "completed_requests_per_s": len(lat) / wall, "p50_ms": pick(0.5), "p99_ms": pick(0.99),
         "mean_ms": float(np.mean(lat)), "statuses": {hf.STATUS_NAMES[k]: status.count(k) for k in set(status)},
         "pool_triangles": sum(len(p.tri_a) + len(p.tri_b) for p in pool),
+    }
+
+
+def bench_body(ctx, args) -> dict:
+    """The body-in-garment pair (about 200k body and 100k cloth triangles), resolved to convergence."""
+    import torch
+
+    import meshgen
+    import paper_1409_2081_amd as hf
+
+    progress("body-garment: generating")
+    pair = meshgen.body_garment()
+    tens = hf.pair_tensors(pair, "cuda:0")
+    kw = dict(tier=pair.tier, max_rounds=64, want_lists=False)
+    for _ in range(2):
+        ctx.resolve(*tens, pair.orientation, pair.d, **kw)
+    torch.cuda.synchronize()
+    lat, stats = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.body_steps):
+        ts = time.perf_counter()
+        g = ctx.resolve(*tens, pair.orientation, pair.d, timing=True, **kw)
+        lat.append(1e3 * (time.perf_counter() - ts))
+        stats.append(g["stats"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s = stats[-1]
+    return {
+        "workload": f"body-in-garment: capsule-union body {len(pair.tri_b)} triangles (oriented), cloth shell "
+                    f"{len(pair.tri_a)} triangles, 5% of cloth vertices pushed in by U[0, 0.03]; float32, "
+                    "float32-filtered, d=1e-3",
+        "converged": s["converged"], "rounds": s["rounds"], "residual_hits": s["residual_hits"],
+        "hits0": s["hits0"], "max_zone": s["max_zone"],
+        "resolved_pairs_per_s": args.body_steps / wall if s["converged"] else 0.0,
+        "ms_per_resolve": 1e3 * wall / args.body_steps, "p50_ms": sorted(lat)[len(lat) // 2],
+        "ef_tests_per_s": sum(x["candidates"] for x in stats) / wall,
+        "stage_ms_per_resolve": {k: sum(x["stage_ms"][k] for x in stats) / len(stats) for k in s["stage_ms"]},
     }
 
 
@@ -241,6 +283,8 @@ def main():
     ap.add_argument("--batch-pairs", type=int, default=256,
                     help="pairs of the mixed pair set in the batched measurement (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=1)
+    ap.add_argument("--body-steps", type=int, default=5,
+                    help="timed resolves of the body-in-garment pair (0: skip it)")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the open-loop serving measurement (0: skip it)")
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -348,6 +392,8 @@ def main():
     }
 
     progress(f"linked tori: {args.steps} steps in {wall:.2f} s")
+    if args.body_steps > 0:
+        out["body_garment"] = bench_body(ctx, args)
     if args.batch_pairs > 0:
         out["batch"] = bench_batch(ctx, args)
     if args.serve_requests > 0:

@@ -121,6 +121,9 @@ def lib():
     """Load libhfcr.so; raises if it has not been built."""
     global _LIB
     if _LIB is None:
+        # load PyTorch's HIP runtime first, so that the library binds to the same
+        # one (two runtimes in one process do not share devices or memory)
+        _torch()
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run paper_1409_2081_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)

@@ -27,8 +27,7 @@ struct DBuf {
 struct Counters {
   uint32_t err;
   uint32_t maxabs[2];
-  uint32_t hit_count[2];
-  uint32_t amb_count[2];
+  uint32_t dir_count[2][2];  // per direction: hits, undecided candidates (cleared together)
   int32_t overflow;
   uint32_t total;
   uint32_t nzones;
@@ -325,15 +324,14 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
     ensure(c->hk[dir], P.hit_cap[dir] * sizeof(uint64_t));
     ensure(c->hv[dir], P.hit_cap[dir] * sizeof(uint32_t));
     ensure(c->amb[dir], P.amb_cap[dir] * sizeof(uint2));
-    HIP_CHECK(hipMemsetAsync(&dc->hit_count[dir], 0, sizeof(uint32_t), c->s));
-    HIP_CHECK(hipMemsetAsync(&dc->amb_count[dir], 0, sizeof(uint32_t), c->s));
+    HIP_CHECK(hipMemsetAsync(dc->dir_count[dir], 0, 2 * sizeof(uint32_t), c->s));
     DcdOut out;
     out.keys = ptr<uint64_t>(c->hk[dir]);
     out.vals = ptr<uint32_t>(c->hv[dir]);
-    out.count = &dc->hit_count[dir];
+    out.count = &dc->dir_count[dir][0];
     out.cap = P.hit_cap[dir];
     out.amb = ptr<uint2>(c->amb[dir]);
-    out.amb_count = &dc->amb_count[dir];
+    out.amb_count = &dc->dir_count[dir][1];
     out.amb_cap = P.amb_cap[dir];
     out.cand = &dc->cand;
     out.f32_unsure = &dc->f32_unsure;
@@ -352,7 +350,7 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
     }
     readback(c);
     if (c->hctr->overflow & 1) throw StatusError{HFCR_E_DEVICE, "BVH traversal stack overflow"};
-    const int64_t nh = c->hctr->hit_count[dir], na = c->hctr->amb_count[dir];
+    const int64_t nh = c->hctr->dir_count[dir][0], na = c->hctr->dir_count[dir][1];
     if (nh <= P.hit_cap[dir] && na <= P.amb_cap[dir]) {
       Scope t(c, 4);
       if (sorted) sort_inplace(c, out.keys, out.vals, nh, 1 + P.hl.bits_e + P.hl.bits_f);
@@ -410,7 +408,7 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
   {
     Scope t(c, 5);
     ensure(c->parent, (size_t)std::max(nvt, 1) * sizeof(int));
-    launch_uf_init(ptr<int>(c->parent), nvt, c->s);
+    launch_uf_init(ptr<int>(c->parent), nvt, &dc->maxk, c->s);
     launch_uf_union(ptr<Constraint>(c->con), S, ptr<int>(c->parent), c->s);
     ensure(c->zkeys, S * sizeof(uint64_t));
     ensure(c->zvals, S * sizeof(uint32_t));
@@ -423,7 +421,6 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
     ensure(c->starts, (S + 1) * sizeof(uint32_t));
     launch_zone_flags(ptr<uint64_t>(c->zkeys), S, bits_s, ptr<uint32_t>(c->flags), c->s);
     scan_u32(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->bsums), nullptr, c->s);
-    HIP_CHECK(hipMemsetAsync(&dc->maxk, 0, sizeof(uint32_t), c->s));
     launch_zone_starts(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->starts), &dc->nzones,
                        &dc->maxk, c->s);
   }

@@ -120,11 +120,21 @@ __device__ inline int narrow(const TravArgs &A, int4 qe, P3f pf, P3f qf, int4 t,
   return ef_test_f64<false>(pd, qd, ad, bd, cd);
 }
 
+// Workgroups are dealt to the XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  Renumbering them so that each XCD takes one contiguous run of
+// workgroups gives each XCD a contiguous range of Morton-ordered queries,
+// i.e. one region of space, so its L2 holds only the part of the face BVH
+// that region touches.  The map is a bijection of [0, n).
+__device__ inline int xcd_contiguous_block(int b, int n) {
+  const int x = b % kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 template <bool F32, bool TIER0, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
   __shared__ int stack[kStack][BLOCK];
   const int tid = threadIdx.x;
-  const int qi = blockIdx.x * BLOCK + tid;
+  const int qi = xcd_contiguous_block((int)blockIdx.x, (int)gridDim.x) * BLOCK + tid;
   if (A.warm && A.nt > 1) {
     unsigned acc = warm_l2(A.nodes, (int64_t)(A.nt - 1) * sizeof(BvhNode), 0u);
     acc = warm_l2(A.leaf_tri, (int64_t)A.nt * sizeof(int4), acc);

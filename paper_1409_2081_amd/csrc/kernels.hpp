@@ -66,7 +66,8 @@ struct Constraint {
 };
 void launch_constraints(const uint64_t *st_keys, int64_t S, StencilLayout sl, const MeshDev &A, const MeshDev &B,
                         double d, Constraint *con, hipStream_t s);
-void launch_uf_init(int *parent, int n, hipStream_t s);
+// Also sets *clear to 0 (may be null).
+void launch_uf_init(int *parent, int n, uint32_t *clear, hipStream_t s);
 void launch_uf_union(const Constraint *con, int64_t S, int *parent, hipStream_t s);
 void launch_zone_keys(const Constraint *con, int64_t S, const int *parent, int bits_s, uint64_t *keys,
                       uint32_t *vals, hipStream_t s);

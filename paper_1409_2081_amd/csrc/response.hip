@@ -158,9 +158,10 @@ __device__ inline void uf_unite(int *P, int a, int b) {
   }
 }
 
-__global__ void k_uf_init(int *parent, int n) {
+__global__ void k_uf_init(int *parent, int n, uint32_t *clear) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) parent[i] = i;
+  if (i == 0 && clear) *clear = 0u;  // the round's largest-zone counter
 }
 
 __global__ void k_uf_union(const Constraint *__restrict__ con, int64_t S, int *parent) {
@@ -172,8 +173,8 @@ __global__ void k_uf_union(const Constraint *__restrict__ con, int64_t S, int *p
   uf_unite(parent, v.x, v.w);
 }
 
-void launch_uf_init(int *parent, int n, hipStream_t s) {
-  if (n > 0) k_uf_init<<<grid_for(n, 256), 256, 0, s>>>(parent, n);
+void launch_uf_init(int *parent, int n, uint32_t *clear, hipStream_t s) {
+  k_uf_init<<<grid_for(n, 256), 256, 0, s>>>(parent, n, clear);
 }
 void launch_uf_union(const Constraint *con, int64_t S, int *parent, hipStream_t s) {
   if (S > 0) k_uf_union<<<grid_for(S, 256), 256, 0, s>>>(con, S, parent);
@@ -313,11 +314,10 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
   const int kp = T * TB;
   // assemble the lower tiles (diagonal tiles: full, the upper half is ignored)
   const int64_t ntile_el = (int64_t)T * (T + 1) / 2 * (TB * TB);
+  int I = 0;  // tile row of this thread's current element, advanced incrementally
   for (int64_t e = tid; e < ntile_el; e += BLOCK) {
     const int64_t t = e >> 6;
     const int rc = (int)(e & 63), r = rc >> 3, c = rc & 7;
-    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((int64_t)I * (I + 1) / 2 > t) --I;
     while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
     const int J = (int)(t - (int64_t)I * (I + 1) / 2);
     const int i = I * TB + r, l = J * TB + c;
@@ -341,45 +341,42 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
   const double thr_u = 1e-6 * dmax;
   for (int J = 0; J < T; ++J) {
     double *D = M + tile_off(J, J);
-    // (1) diagonal tile and the forward substitution of its block, in registers
-    if (tid == 0) {
-      double t[TB][TB], rb[TB], di[TB];
-#pragma unroll
-      for (int r = 0; r < TB; ++r) {
-        rb[r] = rhs[J * TB + r];
-#pragma unroll
-        for (int c = 0; c <= r; ++c) t[r][c] = D[r * TB + c];
-      }
+    // (1) diagonal tile and the forward substitution of its block: wave 0, lane
+    // 8r + c holds element (r, c); lanes 0..7 also hold the block's rhs, y and
+    // 1/L_rr.  Column by column: the pivot is broadcast, the column scaled and
+    // the trailing lower part updated (each value is computed as the serial
+    // column-oriented algorithm computes it).
+    if (tid < kWave) {
+      const int lr = tid >> 3, lc = tid & 7;
+      double val = lr >= lc ? D[lr * TB + lc] : 0.0;
+      double rb = tid < TB ? rhs[J * TB + tid] : 0.0, yv = 0.0, dv = 0.0;
       bool bad = false;
 #pragma unroll
       for (int c = 0; c < TB; ++c) {
-        const double piv = t[c][c];
+        const double piv = __shfl(val, c * TB + c);
         bad = bad || !(piv > thr_u);
         const double l = sqrt(fmax(piv, 0.0)), inv = 1.0 / l;
-        t[c][c] = l;
-        di[c] = inv;
-#pragma unroll
-        for (int r = c + 1; r < TB; ++r) t[r][c] = t[r][c] * inv;
-#pragma unroll
-        for (int r = c + 1; r < TB; ++r)
-#pragma unroll
-          for (int r2 = c + 1; r2 <= r; ++r2) t[r][r2] = t[r][r2] - t[r][c] * t[r2][c];
+        if (lc == c && lr > c) val = val * inv;
+        if (lc == c && lr == c) val = l;
+        const double lrc = __shfl(val, lr * TB + c);   // L[lr][c] (valid for lr > c)
+        const double lcc = __shfl(val, lc * TB + c);   // L[lc][c] (valid for lc > c)
+        if (lr > c && lc > c && lr >= lc) val = val - lrc * lcc;
+        // forward substitution of the block's rhs
+        const double yc = __shfl(rb, c) * inv;
+        const double lrc2 = __shfl(val, (tid < TB ? tid : 0) * TB + c);  // L[r][c] for lane r < 8
+        if (tid == c) {
+          yv = yc;
+          dv = inv;
+        }
+        if (tid < TB && tid > c) rb = rb - lrc2 * yc;
       }
       if (bad) {
-        *flag = 1;
+        if (tid == 0) *flag = 1;
       } else {
-#pragma unroll
-        for (int c = 0; c < TB; ++c) {
-          const double yc = rb[c] * di[c];
-          y[J * TB + c] = yc;
-#pragma unroll
-          for (int r = c + 1; r < TB; ++r) rb[r] = rb[r] - t[r][c] * yc;
-        }
-#pragma unroll
-        for (int r = 0; r < TB; ++r) {
-          dinv[J * TB + r] = di[r];
-#pragma unroll
-          for (int c = 0; c <= r; ++c) D[r * TB + c] = t[r][c];
+        if (lr >= lc) D[lr * TB + lc] = val;
+        if (tid < TB) {
+          y[J * TB + tid] = yv;
+          dinv[J * TB + tid] = dv;
         }
       }
     }
@@ -408,35 +405,35 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
       rhs[I * TB + r] = rhs[I * TB + r] - acc;
     }
     __syncthreads();
-    // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I, one tile row per item
+    // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I, one tile row per
+    // item (the update is latency-bound: many short items beat fewer long ones)
     const int nrem = T - J - 1;
     const int64_t items = (int64_t)nrem * (nrem + 1) / 2 * TB;
+    int u = 0;  // tile row of this thread's current item, advanced incrementally
     for (int64_t it = tid; it < items; it += BLOCK) {
       const int64_t p = it >> 3;
       const int r = (int)(it & 7);
-      int u = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-      while ((int64_t)u * (u + 1) / 2 > p) --u;
       while ((int64_t)(u + 1) * (u + 2) / 2 <= p) ++u;
       const int v = (int)(p - (int64_t)u * (u + 1) / 2);
       const int I = J + 1 + u, K = J + 1 + v;
-      const double *LI = M + tile_off(I, J) + r * TB;
       const double *LK = M + tile_off(K, J);
+      double lk[TB][TB];
+#pragma unroll
+      for (int c = 0; c < TB; ++c)
+#pragma unroll
+        for (int m = 0; m < TB; ++m) lk[c][m] = LK[c * TB + m];
+      const double *LI = M + tile_off(I, J) + r * TB;
       double li[TB];
 #pragma unroll
       for (int m = 0; m < TB; ++m) li[m] = LI[m];
       double *C = M + tile_off(I, K) + r * TB;
-      double out[TB];
-#pragma unroll
-      for (int c = 0; c < TB; ++c) out[c] = C[c];
 #pragma unroll
       for (int c = 0; c < TB; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int m = 0; m < TB; ++m) s = s + li[m] * LK[c * TB + m];
-        out[c] = out[c] - s;
+        for (int m = 0; m < TB; ++m) s = s + li[m] * lk[c][m];
+        C[c] = C[c] - s;
       }
-#pragma unroll
-      for (int c = 0; c < TB; ++c) C[c] = out[c];
     }
     __syncthreads();
   }

@@ -236,6 +236,38 @@ __global__ void k_copy_total(const uint32_t *sums, int nb, const uint32_t *in, c
   (void)nb;
 }
 
+// One-workgroup exclusive scan of in[0..n) into out, total in *total: each
+// of the 1024 threads sums a contiguous chunk, the chunk sums are scanned in
+// LDS, and each chunk is written with its offset.  Used for short inputs,
+// where one launch costs less than three.
+constexpr int64_t kScanOneWgMax = 1 << 14;
+
+__global__ __launch_bounds__(1024) void k_scan_one_wg(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                      int64_t n, uint32_t *total) {
+  __shared__ uint32_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t lo = tid * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  uint32_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += in[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = tid ? part[tid - 1] : 0u;
+  for (int64_t i = lo; i < hi; ++i) {
+    const uint32_t v = in[i];
+    out[i] = run;
+    run += v;
+  }
+  if (total && tid == 1023) *total = part[1023];
+}
+
 size_t scan_block_sums_entries(int64_t n) {
   int64_t nb = (n + kScanTile - 1) / kScanTile;
   return (size_t)(nb < 1 ? 1 : nb);
@@ -243,6 +275,10 @@ size_t scan_block_sums_entries(int64_t n) {
 
 void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *block_sums, uint32_t *total_dev,
               hipStream_t s) {
+  if (n <= kScanOneWgMax) {
+    k_scan_one_wg<<<1, 1024, 0, s>>>(in, out, n, total_dev);
+    return;
+  }
   const int nb = (int)scan_block_sums_entries(n);
   k_scan_reduce<<<nb, kScanBlock, 0, s>>>(in, n, block_sums);
   k_scan_single<<<1, 1024, 0, s>>>(block_sums, nb, nullptr);
