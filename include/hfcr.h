@@ -126,7 +126,8 @@ typedef struct {
 
 #define HFCR_STAT_ROUNDS 64
 #define HFCR_STAGES 8 /* stage_ms: 0 setup+topology, 1 refit, 2 traverse,
-                         3 exact, 4 stencils, 5 zones, 6 solve, 7 update    */
+                         3 narrow phase (filters and exact tier),
+                         4 stencils, 5 zones, 6 solve, 7 update             */
 
 typedef struct {
   int32_t rounds;            /* responses performed                          */
@@ -134,7 +135,8 @@ typedef struct {
   int64_t residual_hits;     /* hits left in the oriented direction(s)       */
   int64_t hits0;             /* round-0 E-F hits (all oriented directions)   */
   int64_t stencils0;         /* round-0 stencils                             */
-  int64_t candidates;        /* narrow-phase E-F tests, all detections       */
+  int64_t candidates;        /* narrow-phase E-F tests, all detections (a
+                                pass redone after a buffer grew counts once) */
   int64_t exact_tests;       /* tests settled by the exact tier              */
   int64_t f32_ambiguous;     /* tests the float32 filter could not settle    */
   int32_t max_zone;          /* largest impact zone seen (stencils)          */
@@ -170,8 +172,8 @@ typedef struct hfcr_ctx hfcr_ctx;
 
 /* Launch schedule of a context (results never depend on it). */
 typedef struct {
-  int32_t trav_block;    /* traversal workgroup size: 64, 128 or 256 (128)  */
-  int32_t trav_warm;     /* 1: warm the L2 with the face BVH first (1)      */
+  int32_t trav_block;    /* traversal workgroup size: 64, 128 or 256 (64)   */
+  int32_t trav_warm;     /* 1: warm the L2 with the face BVH first (0)      */
   int32_t batch_workers; /* pairs in flight at once in the batch calls,
                             each on its own stream, 1..64 (12)              */
   int32_t reserved;

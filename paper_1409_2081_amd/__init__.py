@@ -41,7 +41,7 @@ MAX_ZONE = 4096
 MAX_BATCH = 65536
 STAT_ROUNDS = 64
 STAGES = 8
-STAGE_NAMES = ["setup", "refit", "traverse", "exact", "stencils", "zones", "solve", "update"]
+STAGE_NAMES = ["setup", "refit", "traverse", "narrow", "stencils", "zones", "solve", "update"]
 
 EXPORTED = ["hfcr_default_opts", "hfcr_create", "hfcr_destroy", "hfcr_last_error", "hfcr_detect",
             "hfcr_resolve", "hfcr_resolve_batch", "hfcr_detect_batch", "hfcr_test_orient",

@@ -24,23 +24,24 @@ struct DBuf {
   size_t bytes = 0;
 };
 
+// Counts of one detection pass, cleared together at its start; a pass that
+// overflows a buffer is redone, and only the accepted pass is counted.
+struct PassCount {
+  uint32_t hits, amb, cand_n, pad;
+  unsigned long long cand, f32_unsure, exact, visits;
+};
+
 struct Counters {
   uint32_t err;
   uint32_t maxabs[2];
-  uint32_t dir_count[2][2];  // per direction: hits, undecided candidates (cleared together)
   int32_t overflow;
   uint32_t total;
   uint32_t nzones;
   uint32_t maxk;
   int32_t rank_def;
   int32_t pivoted;
-  uint32_t pad[2];
-  unsigned long long cand;
-  unsigned long long f32_unsure;
-  unsigned long long exact;
-  unsigned long long visits;
   uint32_t max_path;
-  uint32_t pad2;
+  PassCount pass[2];  // per direction
 };
 
 struct Timer {
@@ -69,7 +70,7 @@ struct hfcr_ctx {
   DBuf x64[2], x32[2], edges[2], qedges[2], leaf_tri[2], nodes[2], leaf_parent[2], counters_n[2], root_box[2],
       codes[2], scene_box[2], topo[2];
   // detection
-  DBuf hk[2], hv[2], amb[2];
+  DBuf hk[2], hv[2], amb[2], cand;
   // generic sort / scan scratch
   DBuf sk0, sk1, sv0, sv1, hist, flags, pos, bsums;
   // response
@@ -79,7 +80,7 @@ struct hfcr_ctx {
   std::vector<Timer> timers;
   std::vector<hipEvent_t> free_events;
   bool timing = false;
-  hfcr_tuning tune{128, 1, 12, 0};
+  hfcr_tuning tune{64, 0, 12, 0};
   // batch calls: one context and stream per concurrent worker
   std::vector<hfcr_ctx *> workers;
   std::vector<hipStream_t> wstreams;
@@ -204,8 +205,10 @@ struct Pair {
   bool tier0;
   bool dirty[2];
   bool has_edges[2], has_bvh[2];
-  int64_t hit_cap[2], amb_cap[2];
+  int64_t hit_cap[2], amb_cap[2], cand_cap[2];
   int64_t hits_n[2];
+  // sums over the accepted detection passes
+  int64_t cand = 0, f32_unsure = 0, exact = 0, visits = 0;
 };
 
 void check_mesh(const hfcr_mesh *m, const char *name) {
@@ -324,42 +327,59 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
     ensure(c->hk[dir], P.hit_cap[dir] * sizeof(uint64_t));
     ensure(c->hv[dir], P.hit_cap[dir] * sizeof(uint32_t));
     ensure(c->amb[dir], P.amb_cap[dir] * sizeof(uint2));
-    HIP_CHECK(hipMemsetAsync(dc->dir_count[dir], 0, 2 * sizeof(uint32_t), c->s));
+    ensure(c->cand, P.cand_cap[dir] * sizeof(uint2));
+    // use all of what earlier calls allocated
+    P.hit_cap[dir] = std::max<int64_t>(P.hit_cap[dir], (int64_t)std::min(c->hk[dir].bytes / sizeof(uint64_t),
+                                                                         c->hv[dir].bytes / sizeof(uint32_t)));
+    P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], (int64_t)(c->amb[dir].bytes / sizeof(uint2)));
+    P.cand_cap[dir] = std::max<int64_t>(P.cand_cap[dir], (int64_t)(c->cand.bytes / sizeof(uint2)));
+    PassCount *pc = &dc->pass[dir];
+    HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(PassCount), c->s));
     DcdOut out;
     out.keys = ptr<uint64_t>(c->hk[dir]);
     out.vals = ptr<uint32_t>(c->hv[dir]);
-    out.count = &dc->dir_count[dir][0];
+    out.count = &pc->hits;
     out.cap = P.hit_cap[dir];
     out.amb = ptr<uint2>(c->amb[dir]);
-    out.amb_count = &dc->dir_count[dir][1];
+    out.amb_count = &pc->amb;
     out.amb_cap = P.amb_cap[dir];
-    out.cand = &dc->cand;
-    out.f32_unsure = &dc->f32_unsure;
-    out.exact = &dc->exact;
-    out.visits = &dc->visits;
+    out.cand = &pc->cand;
+    out.f32_unsure = &pc->f32_unsure;
+    out.exact = &pc->exact;
+    out.visits = &pc->visits;
     out.max_path = &dc->max_path;
     out.overflow = &dc->overflow;
     out.warm = c->tune.trav_warm;
+    out.cand_buf = ptr<uint2>(c->cand);
+    out.cand_count = &pc->cand_n;
+    out.cand_cap = P.cand_cap[dir];
     {
       Scope t(c, 2);
       launch_traverse(E, F, dir, P.tier0, P.hl, out, c->tune.trav_block, c->s);
     }
     {
       Scope t(c, 3);
+      launch_narrow(E, F, dir, P.tier0, P.hl, out, c->s);
       launch_exact(E, F, dir, P.hl, out, c->s);
     }
     readback(c);
     if (c->hctr->overflow & 1) throw StatusError{HFCR_E_DEVICE, "BVH traversal stack overflow"};
-    const int64_t nh = c->hctr->dir_count[dir][0], na = c->hctr->dir_count[dir][1];
-    if (nh <= P.hit_cap[dir] && na <= P.amb_cap[dir]) {
+    const PassCount &hp = c->hctr->pass[dir];
+    const int64_t nh = hp.hits, na = hp.amb, nc = hp.cand_n;
+    if (nc <= P.cand_cap[dir] && nh <= P.hit_cap[dir] && na <= P.amb_cap[dir]) {
+      P.cand += (int64_t)hp.cand;
+      P.f32_unsure += (int64_t)hp.f32_unsure;
+      P.exact += (int64_t)hp.exact;
+      P.visits += (int64_t)hp.visits;
       Scope t(c, 4);
       if (sorted) sort_inplace(c, out.keys, out.vals, nh, 1 + P.hl.bits_e + P.hl.bits_f);
       P.hits_n[dir] = nh;
       return nh;
     }
-    // capacity exceeded: grow and redo this pass (candidates are counted twice)
+    // capacity exceeded: grow and redo this pass
     P.hit_cap[dir] = std::max<int64_t>(P.hit_cap[dir], nh + nh / 2 + 64);
     P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], na + na / 2 + 64);
+    P.cand_cap[dir] = std::max<int64_t>(P.cand_cap[dir], nc + nc / 8 + 64);
   }
   throw StatusError{HFCR_E_DEVICE, "hit buffer did not converge"};
 }
@@ -519,6 +539,7 @@ void setup_pair(hfcr_ctx *c, Pair &P, const hfcr_mesh *a, const hfcr_mesh *b, in
     P.has_edges[i] = P.has_bvh[i] = false;
     P.hit_cap[i] = 4096;
     P.amb_cap[i] = 4096;
+    P.cand_cap[i] = 1 << 16;
     P.hits_n[i] = 0;
   }
   ensure(c->ctr, sizeof(Counters));
@@ -639,7 +660,7 @@ void hfcr_destroy(hfcr_ctx *c) {
   for (hipStream_t s : c->wstreams) (void)hipStreamDestroy(s);
   DBuf *all[] = {&c->sk0, &c->sk1, &c->sv0, &c->sv1, &c->hist, &c->flags, &c->pos, &c->bsums, &c->st_keys,
                  &c->st_out_keys, &c->con, &c->parent, &c->zkeys, &c->zvals, &c->starts, &c->lambda, &c->inc_keys,
-                 &c->solve_scratch, &c->ctr};
+                 &c->solve_scratch, &c->ctr, &c->cand};
   for (DBuf *b : all)
     if (b->p) (void)hipFree(b->p);
   for (int i = 0; i < 2; ++i) {
@@ -674,10 +695,10 @@ hfcr_status hfcr_detect(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, int
     write_hit_outputs(c, P, res, st, truncated);
     readback(c);
     if (st) {
-      st->candidates = (int64_t)c->hctr->cand;
-      st->exact_tests = (int64_t)c->hctr->exact;
-      st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
-      st->node_visits = (int64_t)c->hctr->visits;
+      st->candidates = P.cand;
+      st->exact_tests = P.exact;
+      st->f32_ambiguous = P.f32_unsure;
+      st->node_visits = P.visits;
       st->max_query_path = (int32_t)c->hctr->max_path;
       st->converged = st->hits0 == 0;
       st->residual_hits = st->hits0;
@@ -772,11 +793,11 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
       st->rounds = rounds;
       st->converged = converged ? 1 : 0;
       st->residual_hits = converged ? 0 : residual;
-      st->candidates = (int64_t)c->hctr->cand;
-      st->exact_tests = (int64_t)c->hctr->exact;
-      st->f32_ambiguous = (int64_t)c->hctr->f32_unsure;
+      st->candidates = P.cand;
+      st->exact_tests = P.exact;
+      st->f32_ambiguous = P.f32_unsure;
       st->rank_deficient = c->hctr->rank_def;
-      st->node_visits = (int64_t)c->hctr->visits;
+      st->node_visits = P.visits;
       st->max_query_path = (int32_t)c->hctr->max_path;
       st->pivoted_zones = c->hctr->pivoted;
     }

@@ -4,10 +4,12 @@
 //
 // One lane per query edge walks the face BVH depth-first; its stack lives in
 // LDS (one column per lane, so lanes of a wave hit distinct banks).  Every
-// leaf whose box overlaps the segment's box is a candidate and goes through
-// the filtered narrow phase inline.  Hits and undecided candidates are
-// appended with one atomic per wavefront (ballot, popcount, prefix by mbcnt);
-// their order is made deterministic afterwards by sorting the keys.
+// leaf whose box overlaps the segment's box is a candidate; the traversal
+// only queues (query, leaf) pairs, so its loop carries one dependent memory
+// access per step (the node), and a second kernel runs the filtered narrow
+// phase on all queued pairs at once.  Candidates, hits and undecided pairs
+// are appended with one atomic per wavefront (ballot, popcount, prefix by
+// mbcnt); the order is made deterministic afterwards by sorting the keys.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "predicates.hpp"
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
     if (acc == 0x9e3779b9u && qi == -1) atomicOr(A.out.overflow, 2);  // never true for qi >= 0
   }
   const bool valid = qi < A.ne;
-  unsigned long long ncand = 0, unsure32 = 0, nvisit = 0;
+  unsigned long long ncand = 0, nvisit = 0;
   int4 qe = valid ? A.qedges[qi] : make_int4(0, 0, 0, 0);
   P3f pf{}, qf{};
   P3d pd{}, qd{};
@@ -173,7 +175,6 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
   if (A.nt == 1) alive = false;
   int node = 0, sp = 0, top = -1;
   unsigned path = 0;
-  const uint64_t dir_bits = (uint64_t)A.dir << (A.lay.bits_e + A.lay.bits_f);
   while (true) {
     int leaf_a = pending_leaf, leaf_b = -1;
     pending_leaf = -1;
@@ -211,40 +212,25 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
         alive = false;
       }
     }
-    // narrow phase of up to two leaves found at this step (skipped by the
-    // whole wavefront when no lane reached a leaf)
+    // queue up to two candidate leaves found at this step
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      if (!__any((k == 0 ? leaf_a : leaf_b) >= 0)) continue;
       const int leaf = k == 0 ? leaf_a : leaf_b;
-      int res = 0;
-      int4 t = make_int4(0, 0, 0, 0);
-      if (leaf >= 0) {
-        t = A.leaf_tri[leaf];
-        ++ncand;
-        res = narrow<F32, TIER0>(A, qe, pf, qf, t, unsure32);
-      }
-      const bool is_hit = res == 1 || res == 2;
-      const uint32_t slot = wave_append(A.out.count, is_hit);
-      if (is_hit && slot < A.out.cap) {
-        A.out.keys[slot] = dir_bits | ((uint64_t)qe.z << A.lay.bits_f) | (uint32_t)t.w;
-        A.out.vals[slot] = (uint32_t)(res == 1 ? qe.x : qe.y);
-      }
-      const bool is_amb = res == kHitUnsure;
-      const uint32_t aslot = wave_append(A.out.amb_count, is_amb);
-      if (is_amb && aslot < A.out.amb_cap) A.out.amb[aslot] = make_uint2((uint32_t)qi, (uint32_t)leaf);
+      if (!__any(leaf >= 0)) continue;
+      const bool is_cand = leaf >= 0;
+      ncand += is_cand;
+      const uint32_t slot = wave_append(A.out.cand_count, is_cand);
+      if (is_cand && slot < A.out.cand_cap) A.out.cand_buf[slot] = make_uint2((uint32_t)qi, (uint32_t)leaf);
     }
     if (!__any(alive)) break;
   }
   // one counter update per wave
   for (int off = 32; off > 0; off >>= 1) {
     ncand += __shfl_xor(ncand, off);
-    unsure32 += __shfl_xor(unsure32, off);
     nvisit += __shfl_xor(nvisit, off);
   }
   if (__lane_id() == 0) {
     if (ncand) atomicAdd(A.out.cand, ncand);
-    if (unsure32) atomicAdd(A.out.f32_unsure, unsure32);
     if (nvisit) atomicAdd(A.out.visits, nvisit);
   }
   for (int off = 32; off > 0; off >>= 1) path = max(path, (unsigned)__shfl_xor((int)path, off));
@@ -294,6 +280,62 @@ void launch_traverse(const MeshDev &E, const MeshDev &F, int dir, bool tier0, Hi
     launch_traverse_b<128>(E, F, tier0, a, s);
   else
     launch_traverse_b<256>(E, F, tier0, a, s);
+}
+
+// ----------------------------------------------------------- narrow phase
+// Grid-stride over the queued candidates (count read on the device).
+template <bool F32, bool TIER0>
+__global__ __launch_bounds__(256) void k_narrow(TravArgs A) {
+  const uint32_t nc = *A.out.cand_count;
+  const uint32_t n = nc < A.out.cand_cap ? nc : (uint32_t)A.out.cand_cap;
+  const uint64_t dir_bits = (uint64_t)A.dir << (A.lay.bits_e + A.lay.bits_f);
+  unsigned long long unsure32 = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  // every lane of a wave runs the same number of iterations (wave_append)
+  const uint32_t n_round = (n + 63u) & ~63u;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_round; i += stride) {
+    int res = 0;
+    int4 qe = make_int4(0, 0, 0, 0), t = make_int4(0, 0, 0, 0);
+    uint2 item = make_uint2(0, 0);
+    if (i < n) {
+      item = A.out.cand_buf[i];
+      qe = A.qedges[item.x];
+      t = A.leaf_tri[item.y];
+      P3f pf{}, qf{};
+      if (TIER0) {
+        pf = load_f32(A.ex32, A.env, qe.x);
+        qf = load_f32(A.ex32, A.env, qe.y);
+      }
+      res = narrow<F32, TIER0>(A, qe, pf, qf, t, unsure32);
+    }
+    const bool is_hit = res == 1 || res == 2;
+    const uint32_t slot = wave_append(A.out.count, is_hit);
+    if (is_hit && slot < A.out.cap) {
+      A.out.keys[slot] = dir_bits | ((uint64_t)qe.z << A.lay.bits_f) | (uint32_t)t.w;
+      A.out.vals[slot] = (uint32_t)(res == 1 ? qe.x : qe.y);
+    }
+    const bool is_amb = res == kHitUnsure;
+    const uint32_t aslot = wave_append(A.out.amb_count, is_amb);
+    if (is_amb && aslot < A.out.amb_cap) A.out.amb[aslot] = item;
+  }
+  for (int off = 32; off > 0; off >>= 1) unsure32 += __shfl_xor(unsure32, off);
+  if (__lane_id() == 0 && unsure32) atomicAdd(A.out.f32_unsure, unsure32);
+}
+
+void launch_narrow(const MeshDev &E, const MeshDev &F, int dir, bool tier0, HitLayout lay, const DcdOut &out,
+                   hipStream_t s) {
+  if (E.ne <= 0 || F.nt <= 0) return;
+  TravArgs a = make_args(E, F, dir, lay, out);
+  const bool f32 = E.f32 && F.f32 && E.x32 && F.x32;
+  // grid-stride, since the count is only known on the device: about two
+  // candidates per query edge fill the grid once
+  const unsigned grid = std::min<unsigned>(1024u, std::max<unsigned>(8u, grid_for(2 * (int64_t)E.ne, 256)));
+  if (f32 && tier0 && E.small_coords && F.small_coords)
+    k_narrow<true, true><<<grid, 256, 0, s>>>(a);
+  else if (f32)
+    k_narrow<true, false><<<grid, 256, 0, s>>>(a);
+  else
+    k_narrow<false, false><<<grid, 256, 0, s>>>(a);
 }
 
 // ------------------------------------------------------------ exact tier

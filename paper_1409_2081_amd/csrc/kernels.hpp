@@ -40,9 +40,16 @@ struct DcdOut {
   unsigned *max_path;           // longest single-query node count
   int *overflow;         // traversal stack overflow flag
   int warm;              // warm the L2 before traversing
+  uint2 *cand_buf;       // (query index, leaf index) pairs found by the traversal
+  uint32_t *cand_count;  // device counter
+  int64_t cand_cap;
 };
 void launch_traverse(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, bool tier0, HitLayout lay,
                      const DcdOut &out, int block, hipStream_t s);
+// Narrow phase of the candidate pairs the traversal queued (float32 filter,
+// then float64 filter; undecided pairs go to the exact tier).
+void launch_narrow(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, bool tier0, HitLayout lay,
+                   const DcdOut &out, hipStream_t s);
 void launch_exact(const MeshDev &edge_mesh, const MeshDev &face_mesh, int dir, HitLayout lay, const DcdOut &out,
                   hipStream_t s);
 void launch_write_hits(const uint64_t *keys, const uint32_t *vals, int64_t n, HitLayout lay, const int2 *edges_a,
