@@ -24,7 +24,7 @@ It follows J. Ye, "History-free Collision Response for Deformable Surfaces"
   * repair loop (Section 3): detect, relocate, repeat until no E-F
     intersection remains.
 
-Readings of points the paper leaves open (each one is listed in the design doc):
+Readings of points the paper leaves open:
   * the normal n is unit length, so D is a signed distance and d a distance;
   * orientation is given by winding: counter-clockwise (right-hand) = front;
   * when both meshes are oriented the roles alternate between rounds: round r
