@@ -37,7 +37,8 @@ struct Counters {
   int32_t overflow;
   uint32_t total;
   uint32_t nzones;
-  uint32_t maxk;
+  uint32_t maxk;      // cleared with retry_n, which must follow it
+  uint32_t retry_n;   // zones the tiled solve hands to the pivoted one
   int32_t rank_def;
   int32_t pivoted;
   uint32_t max_path;
@@ -74,7 +75,7 @@ struct hfcr_ctx {
   // generic sort / scan scratch
   DBuf sk0, sk1, sv0, sv1, hist, flags, pos, bsums;
   // response
-  DBuf st_keys, st_out_keys, con, parent, zkeys, zvals, starts, lambda, inc_keys, solve_scratch;
+  DBuf st_keys, st_out_keys, con, parent, zkeys, zvals, starts, lambda, inc_keys, solve_scratch, retry;
   DBuf ctr;
   Counters *hctr = nullptr;  // pinned
   std::vector<Timer> timers;
@@ -457,6 +458,7 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
     int nslots = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)info.nzones, 2048, budget / stride}));
     ensure(c->solve_scratch, (size_t)nslots * stride * sizeof(double));
     ensure(c->lambda, S * sizeof(double));
+    ensure(c->retry, (size_t)info.nzones * sizeof(uint32_t));
     SolveArgs a;
     a.con = ptr<Constraint>(c->con);
     a.order = ptr<uint32_t>(c->zvals);
@@ -471,6 +473,8 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
     a.nslots = nslots;
     a.rank_def = &dc->rank_def;
     a.pivoted = &dc->pivoted;
+    a.retry = ptr<uint32_t>(c->retry);
+    a.retry_n = &dc->retry_n;
     a.tau = 1e-12;
     a.maxk = info.maxk;
     launch_solve(a, c->s);
@@ -660,7 +664,7 @@ void hfcr_destroy(hfcr_ctx *c) {
   for (hipStream_t s : c->wstreams) (void)hipStreamDestroy(s);
   DBuf *all[] = {&c->sk0, &c->sk1, &c->sv0, &c->sv1, &c->hist, &c->flags, &c->pos, &c->bsums, &c->st_keys,
                  &c->st_out_keys, &c->con, &c->parent, &c->zkeys, &c->zvals, &c->starts, &c->lambda, &c->inc_keys,
-                 &c->solve_scratch, &c->ctr, &c->cand};
+                 &c->solve_scratch, &c->ctr, &c->cand, &c->retry};
   for (DBuf *b : all)
     if (b->p) (void)hipFree(b->p);
   for (int i = 0; i < 2; ++i) {

@@ -74,6 +74,7 @@ struct Constraint {
 void launch_constraints(const uint64_t *st_keys, int64_t S, StencilLayout sl, const MeshDev &A, const MeshDev &B,
                         double d, Constraint *con, hipStream_t s);
 // Also sets *clear to 0 (may be null).
+// parent[i] = i; also zeroes clear[0] and clear[1] (when clear is not null)
 void launch_uf_init(int *parent, int n, uint32_t *clear, hipStream_t s);
 void launch_uf_union(const Constraint *con, int64_t S, int *parent, hipStream_t s);
 void launch_zone_keys(const Constraint *con, int64_t S, const int *parent, int bits_s, uint64_t *keys,
@@ -95,6 +96,8 @@ struct SolveArgs {
   int nslots;
   int *rank_def;            // count of rank-deficient zones
   int *pivoted;             // zones that needed the pivoted (rank-revealing) path
+  uint32_t *retry;          // [nzones] zones handed from the tiled to the pivoted path
+  uint32_t *retry_n;        // their count (zero before the solve)
   double tau;
   int maxk;                 // largest zone
 };

@@ -161,7 +161,7 @@ __device__ inline void uf_unite(int *P, int a, int b) {
 __global__ void k_uf_init(int *parent, int n, uint32_t *clear) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) parent[i] = i;
-  if (i == 0 && clear) *clear = 0u;  // the round's largest-zone counter
+  if (i < 2 && clear) clear[i] = 0u;  // the round's largest-zone and solve-retry counters
 }
 
 __global__ void k_uf_union(const Constraint *__restrict__ con, int64_t S, int *parent) {
@@ -247,9 +247,11 @@ void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, u
 // (sized at launch for the largest such zone); larger zones keep the matrix
 // in the workgroup's global slot (L2-resident) and the rest in LDS when it
 // fits, else in the slot too.
-constexpr int kSolveBlock = 256;
+constexpr int kSolveBlock = 256;   // pivoted path
+constexpr int kTiledBlock = 1024;  // tiled path: 16 waves, four per SIMD, to hide LDS and FMA latency
+constexpr int kWgBytes = 512;      // per-wave reduction slots (up to 16 waves) and a flag
 constexpr int kZoneLds = 176;
-constexpr int kZoneVecLds = 1024;
+constexpr int kZoneVecLds = 896;  // vectors + kWgBytes + a column of 112 tiles fit in 160 KB
 constexpr int kZoneMax = 4096;  // == HFCR_MAX_ZONE
 
 __device__ inline double inv_mass(int v, const double *wa, const double *wb, int nva) {
@@ -292,23 +294,31 @@ __host__ __device__ inline size_t zone_mat_doubles(int k) {
   return tiled > packed ? tiled : packed;
 }
 __host__ __device__ inline size_t zone_lds_bytes(bool mat_lds, int kcap) {
-  return (mat_lds ? zone_mat_doubles(kcap) * 8 : 0) + zone_vec_bytes(kcap) + 4 * 16 + 64;
+  return (mat_lds ? zone_mat_doubles(kcap) * 8 : 0) + zone_vec_bytes(kcap) + kWgBytes;
 }
 
 // ---- tiled unpivoted Cholesky (fast path) --------------------------------
-// Lower tiles of 8 x 8, tile (I, J) for I >= J at (I(I+1)/2 + J) * 64,
-// row-major inside the tile.  The matrix is padded to a multiple of 8 with
-// diag = max diag A (so padded rows never trip the pivot test) and rhs 0.
+// Lower tiles of 8 x 8, tile (I, J) for I >= J at (I(I+1)/2 + J) * 64.
+// Inside a tile, element (r, c) sits at 8r + (c xor r): the rows are 64 B
+// apart, so without the swizzle the eight rows of a column would fall on
+// the same few LDS banks; with it they fall on eight different ones.  The
+// matrix is padded to a multiple of 8 with diag = max diag A (so padded
+// rows never trip the pivot test) and rhs 0.
 constexpr int TB = 8;
 __device__ inline int64_t tile_off(int I, int J) { return ((int64_t)I * (I + 1) / 2 + J) * (TB * TB); }
+__device__ inline int sw(int r, int c) { return r * TB + (c ^ r); }
 
 // Returns true when every pivot exceeds thr_u; on success lam[0..k) holds the
 // solution.  On failure the matrix storage is garbage (the caller reassembles).
-template <int BLOCK>
+// STAGE (matrix in global memory): each step's factored diagonal tile and
+// column of tiles are also written to LDS (P: 64 + 64 (T - 1) doubles), and
+// the panel and trailing update read them there, so the trailing update's
+// only global accesses are the tile it updates.
+template <int BLOCK, bool STAGE>
 __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny, const double *nz,
                             const int *v0, const int *v1, const int *v2, const int *v3, const double *rr,
                             double *rhs, double *y, double *dinv, double *lam, const SolveArgs &a, double dmax,
-                            int *flag) {
+                            int *flag, double *P) {
   const int tid = threadIdx.x;
   const int T = (k + TB - 1) / TB;
   const int kp = T * TB;
@@ -333,7 +343,7 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
     } else if (i == l) {
       val = dmax > 0.0 ? dmax : 1.0;
     }
-    M[e] = val;
+    M[t * (TB * TB) + sw(r, c)] = val;
   }
   for (int i = tid; i < kp; i += BLOCK) rhs[i] = i < k ? rr[i] : 0.0;
   if (tid == 0) *flag = 0;
@@ -348,7 +358,7 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
     // column-oriented algorithm computes it).
     if (tid < kWave) {
       const int lr = tid >> 3, lc = tid & 7;
-      double val = lr >= lc ? D[lr * TB + lc] : 0.0;
+      double val = lr >= lc ? D[sw(lr, lc)] : 0.0;
       double rb = tid < TB ? rhs[J * TB + tid] : 0.0, yv = 0.0, dv = 0.0;
       bool bad = false;
 #pragma unroll
@@ -373,7 +383,8 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
       if (bad) {
         if (tid == 0) *flag = 1;
       } else {
-        if (lr >= lc) D[lr * TB + lc] = val;
+        if (lr >= lc) D[sw(lr, lc)] = val;
+        if (STAGE) P[sw(lr, lc)] = val;
         if (tid < TB) {
           y[J * TB + tid] = yv;
           dinv[J * TB + tid] = dv;
@@ -385,54 +396,55 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
     // (2) panel: L_IJ = A_IJ L_JJ^-T, and the forward-substitution update
     for (int it = tid; it < (T - J - 1) * TB; it += BLOCK) {
       const int I = J + 1 + it / TB, r = it % TB;
-      double *B = M + tile_off(I, J) + r * TB;
+      double *B = M + tile_off(I, J);
+      const double *Dp = STAGE ? P : D;
       double x[TB];
 #pragma unroll
-      for (int c = 0; c < TB; ++c) x[c] = B[c];
+      for (int c = 0; c < TB; ++c) x[c] = B[sw(r, c)];
 #pragma unroll
       for (int c = 0; c < TB; ++c) {
         double s = x[c];
 #pragma unroll
-        for (int m = 0; m < c; ++m) s = s - x[m] * D[c * TB + m];
+        for (int m = 0; m < c; ++m) s = s - x[m] * Dp[sw(c, m)];
         x[c] = s * dinv[J * TB + c];
       }
       double acc = 0.0;
 #pragma unroll
       for (int c = 0; c < TB; ++c) {
-        B[c] = x[c];
+        B[sw(r, c)] = x[c];
+        if (STAGE) P[(I - J) * (TB * TB) + sw(r, c)] = x[c];
         acc = acc + x[c] * y[J * TB + c];
       }
       rhs[I * TB + r] = rhs[I * TB + r] - acc;
     }
     __syncthreads();
-    // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I, one tile row per
-    // item (the update is latency-bound: many short items beat fewer long ones)
-    const int nrem = T - J - 1;
-    const int64_t items = (int64_t)nrem * (nrem + 1) / 2 * TB;
-    int u = 0;  // tile row of this thread's current item, advanced incrementally
-    for (int64_t it = tid; it < items; it += BLOCK) {
-      const int64_t p = it >> 3;
-      const int r = (int)(it & 7);
-      while ((int64_t)(u + 1) * (u + 2) / 2 <= p) ++u;
-      const int v = (int)(p - (int64_t)u * (u + 1) / 2);
-      const int I = J + 1 + u, K = J + 1 + v;
-      const double *LK = M + tile_off(K, J);
-      double lk[TB][TB];
+    // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I, one
+    // wavefront per tile pair, lane 8r + c computing element (r, c) (the
+    // rows of L_IJ and L_KJ it reads are each shared by eight lanes)
+    {
+      const int nrem = T - J - 1;
+      const int npair = nrem * (nrem + 1) / 2;
+      const int r = (tid & 63) >> 3, c = tid & 7;
+      int u = 0;  // tile row of this wave's current pair, advanced incrementally
+      for (int p = tid >> 6; p < npair; p += BLOCK / 64) {
+        while ((u + 1) * (u + 2) / 2 <= p) ++u;
+        const int v = p - u * (u + 1) / 2;
+        const int I = J + 1 + u, K = J + 1 + v;
+        // 32-bit tile offsets (k <= 4096 keeps them below 2^24)
+        const double *LI = STAGE ? P + (u + 1) * (TB * TB) : M + (I * (I + 1) / 2 + J) * (TB * TB);
+        const double *LK = STAGE ? P + (v + 1) * (TB * TB) : M + (K * (K + 1) / 2 + J) * (TB * TB);
+        double *C = M + (I * (I + 1) / 2 + K) * (TB * TB) + sw(r, c);
+        // every load issued before the first product uses one
+        double li[TB], lk[TB];
 #pragma unroll
-      for (int c = 0; c < TB; ++c)
+        for (int m = 0; m < TB; ++m) li[m] = LI[sw(r, m)];
 #pragma unroll
-        for (int m = 0; m < TB; ++m) lk[c][m] = LK[c * TB + m];
-      const double *LI = M + tile_off(I, J) + r * TB;
-      double li[TB];
-#pragma unroll
-      for (int m = 0; m < TB; ++m) li[m] = LI[m];
-      double *C = M + tile_off(I, K) + r * TB;
-#pragma unroll
-      for (int c = 0; c < TB; ++c) {
+        for (int m = 0; m < TB; ++m) lk[m] = LK[sw(c, m)];
+        const double c0 = *C;
         double s = 0.0;
 #pragma unroll
-        for (int m = 0; m < TB; ++m) s = s + li[m] * lk[c][m];
-        C[c] = C[c] - s;
+        for (int m = 0; m < TB; ++m) s = s + li[m] * lk[m];
+        *C = c0 - s;
       }
     }
     __syncthreads();
@@ -441,18 +453,12 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
   for (int J = T - 1; J >= 0; --J) {
     const double *D = M + tile_off(J, J);
     if (tid == 0) {
-      double t[TB][TB], yb[TB], lb[TB];
-#pragma unroll
-      for (int r = 0; r < TB; ++r) {
-        yb[r] = y[J * TB + r];
-#pragma unroll
-        for (int c = 0; c <= r; ++c) t[r][c] = D[r * TB + c];
-      }
+      double lb[TB];
 #pragma unroll
       for (int c = TB - 1; c >= 0; --c) {
-        double s2 = yb[c];
+        double s2 = y[J * TB + c];
 #pragma unroll
-        for (int m = c + 1; m < TB; ++m) s2 = s2 - t[m][c] * lb[m];
+        for (int m = c + 1; m < TB; ++m) s2 = s2 - D[sw(m, c)] * lb[m];
         lb[c] = s2 * dinv[J * TB + c];
       }
 #pragma unroll
@@ -464,7 +470,7 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
       const double *B = M + tile_off(J, K);
       double s = 0.0;
 #pragma unroll
-      for (int r = 0; r < TB; ++r) s = s + B[r * TB + c] * lam[J * TB + r];
+      for (int r = 0; r < TB; ++r) s = s + B[sw(r, c)] * lam[J * TB + r];
       y[K * TB + c] = y[K * TB + c] - s;
     }
     __syncthreads();
@@ -472,6 +478,75 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
   return true;
 }
 
+// Tiled path of every zone with kmin < k <= kcap; a zone whose tiled
+// factorization meets a small pivot is appended to a.retry for k_solve.
+template <bool MAT_LDS, bool VEC_LDS>
+__global__ __launch_bounds__(kTiledBlock) void k_solve_tiled(SolveArgs a, int kmin, int kcap) {
+  constexpr bool vec_lds = VEC_LDS;  // compile-time, so LDS accesses stay ds_* (never flat)
+  extern __shared__ double dyn[];
+  constexpr int NW = kTiledBlock / 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  double *S_lds = dyn;
+  double *vec_lds_base = dyn + (MAT_LDS ? (int64_t)zone_mat_doubles(kcap) : 0);
+  double *wv = vec_lds_base + (vec_lds ? zone_vec_bytes(kcap) / 8 : 0);
+  int *flag = reinterpret_cast<int *>(wv + NW);
+  constexpr bool stage = !MAT_LDS && VEC_LDS;  // global matrix, LDS to spare for a column of tiles
+  double *P = wv + kWgBytes / 8;
+  for (int z = blockIdx.x; z < a.nzones; z += gridDim.x) {
+    const int st = (int)a.starts[z];
+    const int k = (int)a.starts[z + 1] - st;
+    if (k <= kmin || k > kcap) continue;
+    double *slot = a.scratch + (int64_t)blockIdx.x * a.slot_stride;
+    double *S = MAT_LDS ? S_lds : slot;
+    double *Cm = slot + zone_mat_doubles(k);
+    double *vb = vec_lds ? vec_lds_base : Cm + tri_base(k);
+    const int k8 = round8(k);
+    double *nx = vb, *ny = vb + k8, *nz = vb + 2 * k8, *rr = vb + 3 * k8, *rhs = vb + 4 * k8, *lam = vb + 6 * k8,
+           *y = vb + 7 * k8, *dinv = vb + 8 * k8;
+    int *ib = reinterpret_cast<int *>(vb + kVecDoubles * k8);
+    int *v0 = ib, *v1 = ib + k8, *v2 = ib + 2 * k8, *v3 = ib + 3 * k8;
+    for (int i = tid; i < k; i += kTiledBlock) {
+      const Constraint c = a.con[a.order[st + i]];
+      nx[i] = c.n.x;
+      ny[i] = c.n.y;
+      nz[i] = c.n.z;
+      rr[i] = c.n.w;
+      v0[i] = c.v.x;
+      v1[i] = c.v.y;
+      v2[i] = c.v.z;
+      v3[i] = c.v.w;
+    }
+    __syncthreads();
+    // largest diagonal entry: A_ii = (n_i . n_i) (w_x0 + (w_1 + w_2 + w_3) / 9)
+    double dmax = 0.0;
+    {
+      double v = 0.0;
+      int pos = 0, key = 0;
+      for (int i = tid; i < k; i += kTiledBlock) {
+        const double d = (nx[i] * nx[i] + ny[i] * ny[i] + nz[i] * nz[i]) *
+                         (inv_mass(v0[i], a.w_a, a.w_b, a.nv_a) +
+                          (inv_mass(v1[i], a.w_a, a.w_b, a.nv_a) + inv_mass(v2[i], a.w_a, a.w_b, a.nv_a) +
+                           inv_mass(v3[i], a.w_a, a.w_b, a.nv_a)) / 9.0);
+        v = fmax(v, d);
+      }
+      wave_argmax(v, pos, key);
+      if (lane == 0) wv[wave] = v;
+      __syncthreads();
+      for (int w = 0; w < NW; ++w) dmax = fmax(dmax, wv[w]);
+      __syncthreads();
+    }
+    if (tiled_solve<kTiledBlock, stage>(S, k, nx, ny, nz, v0, v1, v2, v3, rr, rhs, y, dinv, lam, a, dmax, flag, P)) {
+      for (int i = tid; i < k; i += kTiledBlock) a.lambda[a.order[st + i]] = lam[i];
+    } else if (tid == 0) {
+      atomicAdd(a.pivoted, 1);
+      a.retry[atomicAdd(a.retry_n, 1u)] = (uint32_t)z;
+    }
+    __syncthreads();
+  }
+}
+
+// Pivoted (rank-revealing) path of the zones the tiled path handed over.
 template <bool MAT_LDS, bool VEC_LDS>
 __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, int kcap) {
   constexpr bool vec_lds = VEC_LDS;  // compile-time, so LDS accesses stay ds_* (never flat)
@@ -487,10 +562,12 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
   int *wp = reinterpret_cast<int *>(wv + NW);
   int *wk = wp + NW;
   int *flag = wk + NW;
-  for (int z = blockIdx.x; z < a.nzones; z += gridDim.x) {
+  const uint32_t nretry = *a.retry_n;
+  for (uint32_t q = blockIdx.x; q < nretry; q += gridDim.x) {
+    const int z = (int)a.retry[q];
     const int st = (int)a.starts[z];
     const int k = (int)a.starts[z + 1] - st;
-    if (k <= kmin || k > kcap) continue;
+    if (k <= kmin || k > kcap) continue;  // another class's zone
     double *slot = a.scratch + (int64_t)blockIdx.x * a.slot_stride;
     double *S = MAT_LDS ? S_lds : slot;
     double *Cm = slot + zone_mat_doubles(k);  // rank-deficient case only (packed r x r)
@@ -517,31 +594,8 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
       rem0[i] = i;
     }
     __syncthreads();
-    // largest diagonal entry: A_ii = (n_i . n_i) (w_x0 + (w_1 + w_2 + w_3) / 9)
     double dmax = 0.0;
-    {
-      double v = 0.0;
-      int pos = 0, key = 0;
-      for (int i = tid; i < k; i += kSolveBlock) {
-        const double d = (nx[i] * nx[i] + ny[i] * ny[i] + nz[i] * nz[i]) *
-                         (inv_mass(v0[i], a.w_a, a.w_b, a.nv_a) +
-                          (inv_mass(v1[i], a.w_a, a.w_b, a.nv_a) + inv_mass(v2[i], a.w_a, a.w_b, a.nv_a) +
-                           inv_mass(v3[i], a.w_a, a.w_b, a.nv_a)) / 9.0);
-        v = fmax(v, d);
-      }
-      wave_argmax(v, pos, key);
-      if (lane == 0) wv[wave] = v;
-      __syncthreads();
-      for (int w = 0; w < NW; ++w) dmax = fmax(dmax, wv[w]);
-      __syncthreads();
-    }
-    if (tiled_solve<kSolveBlock>(S, k, nx, ny, nz, v0, v1, v2, v3, rr, rhs, y, dinv, lam, a, dmax, flag)) {
-      for (int i = tid; i < k; i += kSolveBlock) a.lambda[a.order[st + i]] = lam[i];
-      __syncthreads();
-      continue;
-    }
-    // fallback: Cholesky with diagonal pivoting (rank-revealing)
-    if (tid == 0) atomicAdd(a.pivoted, 1);
+    // Cholesky with diagonal pivoting (rank-revealing)
     for (int i = tid; i < k; i += kSolveBlock) {
       rhs[i] = rr[i];
       step_of[i] = k;
@@ -795,14 +849,19 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
 
 template <bool MAT_LDS, bool VEC_LDS>
 static void launch_class(const SolveArgs &a, int kmin, int kcap, int grid, hipStream_t s) {
-  const size_t bytes = MAT_LDS ? zone_lds_bytes(true, kcap) : (VEC_LDS ? zone_vec_bytes(kcap) : 0) + 4 * 16 + 64;
+  const size_t bytes = MAT_LDS ? zone_lds_bytes(true, kcap) : (VEC_LDS ? zone_vec_bytes(kcap) : 0) + kWgBytes;
+  // the tiled kernel of the global-matrix class with LDS vectors also stages a column of tiles
+  const size_t tiled_bytes = bytes + (!MAT_LDS && VEC_LDS ? (size_t)((kcap + TB - 1) / TB) * TB * TB * 8 : 0);
   // the attribute is per function; set once (thread-safe static initialisation)
   static const bool attr_set = [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve_tiled<MAT_LDS, VEC_LDS>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solve<MAT_LDS, VEC_LDS>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     return true;
   }();
   (void)attr_set;
+  k_solve_tiled<MAT_LDS, VEC_LDS><<<grid, kTiledBlock, tiled_bytes, s>>>(a, kmin, kcap);
   k_solve<MAT_LDS, VEC_LDS><<<grid, kSolveBlock, bytes, s>>>(a, kmin, kcap);
 }
 
