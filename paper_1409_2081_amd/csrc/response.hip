@@ -308,6 +308,14 @@ constexpr int TB = 8;
 __device__ inline int64_t tile_off(int I, int J) { return ((int64_t)I * (I + 1) / 2 + J) * (TB * TB); }
 __device__ inline int sw(int r, int c) { return r * TB + (c ^ r); }
 
+// Value of v in lane `lane` (a compile-time or wave-uniform index).
+__device__ inline double read_lane(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Returns true when every pivot exceeds thr_u; on success lam[0..k) holds the
 // solution.  On failure the matrix storage is garbage (the caller reassembles).
 // STAGE (matrix in global memory): each step's factored diagonal tile and
@@ -351,44 +359,50 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
   const double thr_u = 1e-6 * dmax;
   for (int J = 0; J < T; ++J) {
     double *D = M + tile_off(J, J);
-    // (1) diagonal tile and the forward substitution of its block: wave 0, lane
-    // 8r + c holds element (r, c); lanes 0..7 also hold the block's rhs, y and
-    // 1/L_rr.  Column by column: the pivot is broadcast, the column scaled and
-    // the trailing lower part updated (each value is computed as the serial
-    // column-oriented algorithm computes it).
+    // (1) diagonal tile and the forward substitution of its block: lane r < 8
+    // of wave 0 holds row r of the tile, its rhs entry, y_r and 1/L_rr.
+    // Column by column: the pivot is read from its lane, the column scaled
+    // and the trailing lower part updated, each value computed as the serial
+    // column-oriented algorithm computes it.  Values move between lanes by
+    // lane reads (scalar registers), not through LDS.
     if (tid < kWave) {
-      const int lr = tid >> 3, lc = tid & 7;
-      double val = lr >= lc ? D[sw(lr, lc)] : 0.0;
-      double rb = tid < TB ? rhs[J * TB + tid] : 0.0, yv = 0.0, dv = 0.0;
+      const int r = tid;
+      double row[TB];
+#pragma unroll
+      for (int c = 0; c < TB; ++c) row[c] = (r < TB && r >= c) ? D[sw(r, c)] : 0.0;
+      double rb = r < TB ? rhs[J * TB + r] : 0.0, yv = 0.0, dv = 0.0;
       bool bad = false;
 #pragma unroll
       for (int c = 0; c < TB; ++c) {
-        const double piv = __shfl(val, c * TB + c);
+        const double piv = read_lane(row[c], c);
         bad = bad || !(piv > thr_u);
         const double l = sqrt(fmax(piv, 0.0)), inv = 1.0 / l;
-        if (lc == c && lr > c) val = val * inv;
-        if (lc == c && lr == c) val = l;
-        const double lrc = __shfl(val, lr * TB + c);   // L[lr][c] (valid for lr > c)
-        const double lcc = __shfl(val, lc * TB + c);   // L[lc][c] (valid for lc > c)
-        if (lr > c && lc > c && lr >= lc) val = val - lrc * lcc;
+        if (r > c) row[c] = row[c] * inv;
+        if (r == c) row[c] = l;
+#pragma unroll
+        for (int cc = c + 1; cc < TB; ++cc) {
+          const double lcc = read_lane(row[c], cc);  // L[cc][c]
+          if (r >= cc) row[cc] = row[cc] - row[c] * lcc;
+        }
         // forward substitution of the block's rhs
-        const double yc = __shfl(rb, c) * inv;
-        const double lrc2 = __shfl(val, (tid < TB ? tid : 0) * TB + c);  // L[r][c] for lane r < 8
-        if (tid == c) {
+        const double yc = read_lane(rb, c) * inv;
+        if (r == c) {
           yv = yc;
           dv = inv;
         }
-        if (tid < TB && tid > c) rb = rb - lrc2 * yc;
+        if (r < TB && r > c) rb = rb - row[c] * yc;
       }
       if (bad) {
         if (tid == 0) *flag = 1;
-      } else {
-        if (lr >= lc) D[sw(lr, lc)] = val;
-        if (STAGE) P[sw(lr, lc)] = val;
-        if (tid < TB) {
-          y[J * TB + tid] = yv;
-          dinv[J * TB + tid] = dv;
-        }
+      } else if (r < TB) {
+#pragma unroll
+        for (int c = 0; c < TB; ++c)
+          if (c <= r) {
+            D[sw(r, c)] = row[c];
+            if (STAGE) P[sw(r, c)] = row[c];
+          }
+        y[J * TB + r] = yv;
+        dinv[J * TB + r] = dv;
       }
     }
     __syncthreads();
