@@ -5,9 +5,9 @@
 // One lane per query edge walks the face BVH depth-first; its stack lives in
 // LDS (one column per lane, so lanes of a wave hit distinct banks).  Every
 // leaf whose box overlaps the segment's box is a candidate; the traversal
-// only queues (query, leaf) pairs, so its loop carries one dependent memory
-// access per step (the node), and a second kernel runs the filtered narrow
-// phase on all queued pairs at once.  Candidates, hits and undecided pairs
+// only queues (query, leaf) pairs, staged in LDS and written in batches, so
+// its loop carries one dependent memory access per step (the node), and a
+// second kernel runs the filtered narrow phase on all queued pairs at once.  Candidates, hits and undecided pairs
 // are appended with one atomic per wavefront (ballot, popcount, prefix by
 // mbcnt); the order is made deterministic afterwards by sorting the keys.
 #include "common.hpp"
@@ -132,10 +132,31 @@ __device__ inline int xcd_contiguous_block(int b, int n) {
   return x * q + (x < r ? x : r) + b / kXcds;
 }
 
+// Candidates are staged per wavefront in LDS and written out in batches, so
+// the step loop carries no global atomic: a batch is flushed (one atomic for
+// the wavefront) when fewer than two steps' worth of slots remain, and at the
+// end.
+constexpr int kCandStage = 256;
+
+template <int BLOCK>
+__device__ inline void flush_candidates(const TravArgs &A, uint2 *stage, int &cn) {
+  __builtin_amdgcn_wave_barrier();
+  uint32_t base = 0;
+  if (__lane_id() == 0) base = atomicAdd(A.out.cand_count, (uint32_t)cn);
+  base = (uint32_t)__shfl((int)base, 0);
+  for (int j = (int)__lane_id(); j < cn; j += kWave)
+    if (base + (uint32_t)j < A.out.cand_cap) A.out.cand_buf[base + j] = stage[j];
+  __builtin_amdgcn_wave_barrier();
+  cn = 0;
+}
+
 template <bool F32, bool TIER0, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
   __shared__ int stack[kStack][BLOCK];
+  __shared__ uint2 cstage[BLOCK / kWave][kCandStage];
   const int tid = threadIdx.x;
+  uint2 *stage = cstage[tid / kWave];
+  int cn = 0;  // candidates staged by this wavefront (wave-uniform)
   const int qi = xcd_contiguous_block((int)blockIdx.x, (int)gridDim.x) * BLOCK + tid;
   if (A.warm && A.nt > 1) {
     unsigned acc = warm_l2(A.nodes, (int64_t)(A.nt - 1) * sizeof(BvhNode), 0u);
@@ -212,18 +233,22 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
         alive = false;
       }
     }
-    // queue up to two candidate leaves found at this step
+    // stage up to two candidate leaves found at this step
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int leaf = k == 0 ? leaf_a : leaf_b;
-      if (!__any(leaf >= 0)) continue;
-      const bool is_cand = leaf >= 0;
-      ncand += is_cand;
-      const uint32_t slot = wave_append(A.out.cand_count, is_cand);
-      if (is_cand && slot < A.out.cand_cap) A.out.cand_buf[slot] = make_uint2((uint32_t)qi, (uint32_t)leaf);
+      const uint64_t m = __ballot(leaf >= 0);
+      if (m == 0) continue;
+      if (leaf >= 0) {
+        ++ncand;
+        stage[cn + __popcll(m & lanemask_lt())] = make_uint2((uint32_t)qi, (uint32_t)leaf);
+      }
+      cn += __popcll(m);
     }
+    if (cn > kCandStage - 2 * kWave) flush_candidates<BLOCK>(A, stage, cn);
     if (!__any(alive)) break;
   }
+  if (cn > 0) flush_candidates<BLOCK>(A, stage, cn);
   // one counter update per wave
   for (int off = 32; off > 0; off >>= 1) {
     ncand += __shfl_xor(ncand, off);
