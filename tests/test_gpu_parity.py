@@ -146,6 +146,26 @@ def test_lockstep_sphere_sheet_float64(hfcr_ctx):
     assert rank_def > 0
 
 
+def test_largest_zone_round_matches_oracle(hfcr_ctx):
+    # round 18 of the sphere-sheet pair builds one rank-deficient impact zone
+    # of 4074 stencils, next to the dense solver's 4096 limit: matrix and
+    # vectors in global scratch, tiled attempt, then the pivoted path
+    pair = meshgen.sphere_sheet()
+    pre = oracle.resolve_pair(pair, nthreads=8, max_rounds=18)
+    xa, xb = pre["pos_a"], pre["pos_b"]
+    g = hfcr_ctx.resolve(_t(xa), _t(pair.tri_a), _t(xb), _t(pair.tri_b), pair.orientation, pair.d, max_rounds=1,
+                         round_offset=18, tier=1)
+    o = oracle.resolve(xa, pair.tri_a, xb, pair.tri_b, pair.orientation, pair.d, pair.dtype, max_rounds=1,
+                       nthreads=8, round_offset=18)
+    assert o["per_round"][0]["max_k"] == 4074
+    assert g["stats"]["max_zone"] == 4074 and g["stats"]["rank_deficient"] >= 1
+    assert np.array_equal(_np(g["hits"]), o["hits0"])
+    assert np.array_equal(_np(g["stencils"]), o["stencils0"])
+    err = max(np.abs(_np(g["pos_a"]) - o["pos_a"]).max(), np.abs(_np(g["pos_b"]) - o["pos_b"]).max()) / _diag(pair)
+    print("largest zone round: rel err", err)
+    assert err <= 1e-6, err
+
+
 def test_lockstep_linked_tori_float32(hfcr_ctx):
     worst, _ = _lockstep(hfcr_ctx, meshgen.linked_tori(), 12, tier=0)
     print("linked_tori max rel err", worst)
