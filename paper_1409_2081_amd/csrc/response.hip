@@ -561,12 +561,15 @@ __global__ __launch_bounds__(kTiledBlock) void k_solve_tiled(SolveArgs a, int km
 }
 
 // Pivoted (rank-revealing) path of the zones the tiled path handed over.
+// The matrix-in-LDS class keeps 256 threads (its trailing update holds a
+// row block in registers); the global-matrix classes use 1024.
 template <bool MAT_LDS, bool VEC_LDS>
-__global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, int kcap) {
+__global__ __launch_bounds__(MAT_LDS ? kSolveBlock : kTiledBlock) void k_solve(SolveArgs a, int kmin, int kcap) {
+  constexpr int BLOCK = MAT_LDS ? kSolveBlock : kTiledBlock;
   constexpr bool vec_lds = VEC_LDS;  // compile-time, so LDS accesses stay ds_* (never flat)
   extern __shared__ double dyn[];
   constexpr int TY = 16;  // 16 x 16 tiling of the trailing update
-  constexpr int NW = kSolveBlock / 64;
+  constexpr int NW = BLOCK / 64;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int tx = tid % TY, ty = tid / TY;
@@ -593,7 +596,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
     int *v0 = ib, *v1 = ib + k8, *v2 = ib + 2 * k8, *v3 = ib + 3 * k8, *piv = ib + 4 * k8, *step_of = ib + 5 * k8,
         *rem0 = ib + 6 * k8, *rem1 = ib + 7 * k8;
     // stage the zone's constraints
-    for (int i = tid; i < k; i += kSolveBlock) {
+    for (int i = tid; i < k; i += BLOCK) {
       const Constraint c = a.con[a.order[st + i]];
       nx[i] = c.n.x;
       ny[i] = c.n.y;
@@ -610,14 +613,14 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
     __syncthreads();
     double dmax = 0.0;
     // Cholesky with diagonal pivoting (rank-revealing)
-    for (int i = tid; i < k; i += kSolveBlock) {
+    for (int i = tid; i < k; i += BLOCK) {
       rhs[i] = rr[i];
       step_of[i] = k;
       rem0[i] = i;
     }
     __syncthreads();
     // assemble the packed lower triangle
-    for (int i = ty; i < k; i += kSolveBlock / TY) {
+    for (int i = ty; i < k; i += BLOCK / TY) {
       const int vi[4] = {v0[i], v1[i], v2[i], v3[i]};
       double wi[4];
       for (int s = 0; s < 4; ++s) wi[s] = inv_mass(vi[s], a.w_a, a.w_b, a.nv_a) * coef(s);
@@ -637,7 +640,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
     {
       double v = -1.0;
       int pos = -1, key = -1;
-      for (int i = tid; i < k; i += kSolveBlock) {
+      for (int i = tid; i < k; i += BLOCK) {
         const double d = S[tri_base(i) + i];
         if (d > v) { v = d; pos = i; key = i; }
       }
@@ -671,7 +674,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
       const double inv = 1.0 / lpp;
       const double yj = rhs[p] * inv;  // forward substitution, step j
       // B: column p of L and the stable compaction of the remaining list
-      for (int q = tid; q < nrem; q += kSolveBlock) {
+      for (int q = tid; q < nrem; q += BLOCK) {
         if (q == q0) continue;
         const int i = rem[q];
         const int64_t at = lp(i, p);
@@ -736,8 +739,8 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
           }
         }
       } else {
-        constexpr int CH = 8;  // columns loaded per batch
-        for (int r = ty; r < nr; r += kSolveBlock / TY) {
+        constexpr int CH = 4;  // columns loaded per batch
+        for (int r = ty; r < nr; r += BLOCK / TY) {
           const int i = rem2[r];
           const double li = lcol[r];
           if (tx == 0) rhs[i] = rhs[i] - li * yj;
@@ -775,7 +778,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
     if (rank == k) {
       // backward: L~^T lambda~ = y
       if (MAT_LDS) {
-        // k <= kSolveBlock here: thread tid owns y[tid] in a register
+        // k <= BLOCK here: thread tid owns y[tid] in a register
         const int my_p = tid < k ? piv[tid] : 0;
         double my_y = tid < k ? y[tid] : 0.0;
         for (int j = k - 1; j >= 0; --j) {
@@ -794,7 +797,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
         for (int j = k - 1; j >= 0; --j) {
           const int pj = piv[j];
           const double lj = y[j] * dinv[j];
-          for (int jj = tid; jj < j; jj += kSolveBlock) y[jj] = y[jj] - S[lp(pj, piv[jj])] * lj;
+          for (int jj = tid; jj < j; jj += BLOCK) y[jj] = y[jj] - S[lp(pj, piv[jj])] * lj;
           if (tid == 0) lam[pj] = lj;
           __syncthreads();
         }
@@ -803,15 +806,15 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
       if (tid == 0) atomicAdd(a.rank_def, 1);
       const int r = rank;
       // row order: pivots, then the never-pivoted indices (in index order)
-      for (int q = tid; q < k - r; q += kSolveBlock) piv[r + q] = rem[q];
+      for (int q = tid; q < k - r; q += BLOCK) piv[r + q] = rem[q];
       __syncthreads();
 #define LT(aa, jj) ((aa) < (jj) ? 0.0 : S[lp(piv[(aa)], piv[(jj)])])
-      for (int j = tid; j < r; j += kSolveBlock) {  // y = L~^T r~
+      for (int j = tid; j < r; j += BLOCK) {  // y = L~^T r~
         double acc = 0.0;
         for (int aa = j; aa < k; ++aa) acc += LT(aa, j) * rr[piv[aa]];
         y[j] = acc;
       }
-      for (int j1 = ty; j1 < r; j1 += kSolveBlock / TY)  // C = L~^T L~ (packed lower)
+      for (int j1 = ty; j1 < r; j1 += BLOCK / TY)  // C = L~^T L~ (packed lower)
         for (int j2 = tx; j2 <= j1; j2 += TY) {
           double acc = 0.0;
           for (int aa = j1; aa < k; ++aa) acc += LT(aa, j1) * LT(aa, j2);
@@ -822,9 +825,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
         const double cjj = sqrt(Cm[tri_base(j) + j]);
         __syncthreads();
         if (tid == 0) Cm[tri_base(j) + j] = cjj;
-        for (int i = j + 1 + tid; i < r; i += kSolveBlock) Cm[tri_base(i) + j] = Cm[tri_base(i) + j] / cjj;
+        for (int i = j + 1 + tid; i < r; i += BLOCK) Cm[tri_base(i) + j] = Cm[tri_base(i) + j] / cjj;
         __syncthreads();
-        for (int i = j + 1 + ty; i < r; i += kSolveBlock / TY) {
+        for (int i = j + 1 + ty; i < r; i += BLOCK / TY) {
           const double lij = Cm[tri_base(i) + j];
           for (int l = j + 1 + tx; l <= i; l += TY)
             Cm[tri_base(i) + l] = Cm[tri_base(i) + l] - lij * Cm[tri_base(l) + j];
@@ -835,19 +838,19 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
         for (int j = 0; j < r; ++j) {
           const double yj = y[j] / Cm[tri_base(j) + j];
           __syncthreads();
-          for (int i = j + 1 + tid; i < r; i += kSolveBlock) y[i] = y[i] - Cm[tri_base(i) + j] * yj;
+          for (int i = j + 1 + tid; i < r; i += BLOCK) y[i] = y[i] - Cm[tri_base(i) + j] * yj;
           if (tid == 0) y[j] = yj;
           __syncthreads();
         }
         for (int j = r - 1; j >= 0; --j) {
           const double lj = y[j] / Cm[tri_base(j) + j];
           __syncthreads();
-          for (int i = tid; i < j; i += kSolveBlock) y[i] = y[i] - Cm[tri_base(j) + i] * lj;
+          for (int i = tid; i < j; i += BLOCK) y[i] = y[i] - Cm[tri_base(j) + i] * lj;
           if (tid == 0) y[j] = lj;
           __syncthreads();
         }
       }
-      for (int aa = tid; aa < k; aa += kSolveBlock) {  // lambda~ = L~ u
+      for (int aa = tid; aa < k; aa += BLOCK) {  // lambda~ = L~ u
         double acc = 0.0;
         const int jm = aa < r - 1 ? aa : r - 1;
         for (int j = 0; j <= jm; ++j) acc += LT(aa, j) * y[j];
@@ -856,7 +859,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a, int kmin, in
 #undef LT
     }
     __syncthreads();
-    for (int i = tid; i < k; i += kSolveBlock) a.lambda[a.order[st + i]] = lam[i];
+    for (int i = tid; i < k; i += BLOCK) a.lambda[a.order[st + i]] = lam[i];
     __syncthreads();
   }
 }
@@ -876,7 +879,7 @@ static void launch_class(const SolveArgs &a, int kmin, int kcap, int grid, hipSt
   }();
   (void)attr_set;
   k_solve_tiled<MAT_LDS, VEC_LDS><<<grid, kTiledBlock, tiled_bytes, s>>>(a, kmin, kcap);
-  k_solve<MAT_LDS, VEC_LDS><<<grid, kSolveBlock, bytes, s>>>(a, kmin, kcap);
+  k_solve<MAT_LDS, VEC_LDS><<<grid, MAT_LDS ? kSolveBlock : kTiledBlock, bytes, s>>>(a, kmin, kcap);
 }
 
 void launch_solve(const SolveArgs &a, hipStream_t s) {
