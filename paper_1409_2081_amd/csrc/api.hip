@@ -390,6 +390,18 @@ int64_t build_stencils(hfcr_ctx *c, Pair &P, const int *dirs, int nd, DBuf &dst)
   int64_t n = 0;
   for (int q = 0; q < nd; ++q) n += P.hits_n[dirs[q]];
   if (n == 0) return 0;
+  {
+    const int d0 = dirs[0], d1 = nd > 1 ? dirs[1] : dirs[0];
+    const int64_t n1 = nd > 1 ? P.hits_n[d1] : 0;
+    ensure(dst, n * sizeof(uint64_t));
+    Counters *dc = ptr<Counters>(c->ctr);
+    if (launch_stencils_small(ptr<uint64_t>(c->hk[d0]), ptr<uint32_t>(c->hv[d0]), P.hits_n[d0],
+                              ptr<uint64_t>(c->hk[d1]), ptr<uint32_t>(c->hv[d1]), n1, P.hl, P.sl, ptr<uint64_t>(dst),
+                              &dc->total, c->s)) {
+      readback(c);
+      return c->hctr->total;
+    }
+  }
   ensure(c->sk0, n * sizeof(uint64_t));
   ensure(c->flags, n * sizeof(uint32_t));
   int64_t off = 0;
@@ -429,21 +441,24 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
   {
     Scope t(c, 5);
     ensure(c->parent, (size_t)std::max(nvt, 1) * sizeof(int));
-    launch_uf_init(ptr<int>(c->parent), nvt, &dc->maxk, c->s);
-    launch_uf_union(ptr<Constraint>(c->con), S, ptr<int>(c->parent), c->s);
     ensure(c->zkeys, S * sizeof(uint64_t));
     ensure(c->zvals, S * sizeof(uint32_t));
-    launch_zone_keys(ptr<Constraint>(c->con), S, ptr<int>(c->parent), bits_s, ptr<uint64_t>(c->zkeys),
-                     ptr<uint32_t>(c->zvals), c->s);
-    sort_inplace(c, ptr<uint64_t>(c->zkeys), ptr<uint32_t>(c->zvals), S, bits_s + bits_for(nvt));
-    ensure(c->flags, S * sizeof(uint32_t));
-    ensure(c->pos, S * sizeof(uint32_t));
-    ensure(c->bsums, scan_block_sums_entries(S) * sizeof(uint32_t));
     ensure(c->starts, (S + 1) * sizeof(uint32_t));
-    launch_zone_flags(ptr<uint64_t>(c->zkeys), S, bits_s, ptr<uint32_t>(c->flags), c->s);
-    scan_u32(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->bsums), nullptr, c->s);
-    launch_zone_starts(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->starts), &dc->nzones,
-                       &dc->maxk, c->s);
+    if (!launch_zones_small(ptr<Constraint>(c->con), S, ptr<int>(c->parent), bits_s, ptr<uint64_t>(c->zkeys),
+                            ptr<uint32_t>(c->zvals), ptr<uint32_t>(c->starts), &dc->nzones, &dc->maxk, c->s)) {
+      launch_uf_init(ptr<int>(c->parent), nvt, &dc->maxk, c->s);
+      launch_uf_union(ptr<Constraint>(c->con), S, ptr<int>(c->parent), c->s);
+      launch_zone_keys(ptr<Constraint>(c->con), S, ptr<int>(c->parent), bits_s, ptr<uint64_t>(c->zkeys),
+                       ptr<uint32_t>(c->zvals), c->s);
+      sort_inplace(c, ptr<uint64_t>(c->zkeys), ptr<uint32_t>(c->zvals), S, bits_s + bits_for(nvt));
+      ensure(c->flags, S * sizeof(uint32_t));
+      ensure(c->pos, S * sizeof(uint32_t));
+      ensure(c->bsums, scan_block_sums_entries(S) * sizeof(uint32_t));
+      launch_zone_flags(ptr<uint64_t>(c->zkeys), S, bits_s, ptr<uint32_t>(c->flags), c->s);
+      scan_u32(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->bsums), nullptr, c->s);
+      launch_zone_starts(ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), S, ptr<uint32_t>(c->starts),
+                         &dc->nzones, &dc->maxk, c->s);
+    }
   }
   readback(c);
   info.nzones = (int)c->hctr->nzones;

@@ -77,11 +77,21 @@ void launch_constraints(const uint64_t *st_keys, int64_t S, StencilLayout sl, co
 // parent[i] = i; also zeroes clear[0] and clear[1] (when clear is not null)
 void launch_uf_init(int *parent, int n, uint32_t *clear, hipStream_t s);
 void launch_uf_union(const Constraint *con, int64_t S, int *parent, hipStream_t s);
+// Stencil keys of up to two hit lists, sorted and made unique, written to
+// out (room for n0 + n1 keys) with their count in *total, in one launch when
+// n0 + n1 <= 1024; returns false (and launches nothing) otherwise.
+bool launch_stencils_small(const uint64_t *hk0, const uint32_t *hv0, int64_t n0, const uint64_t *hk1,
+                           const uint32_t *hv1, int64_t n1, HitLayout hl, StencilLayout sl, uint64_t *out,
+                           uint32_t *total, hipStream_t s);
 void launch_zone_keys(const Constraint *con, int64_t S, const int *parent, int bits_s, uint64_t *keys,
                       uint32_t *vals, hipStream_t s);
 void launch_zone_flags(const uint64_t *keys, int64_t S, int bits_s, uint32_t *flags, hipStream_t s);
 void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, uint32_t *starts,
                         uint32_t *nzones_out, uint32_t *maxk_out, hipStream_t s);
+// The zone stage (uf_init .. zone_starts) in one launch when S is small
+// enough; returns false (and launches nothing) otherwise.
+bool launch_zones_small(const Constraint *con, int64_t S, int *parent, int bits_s, uint64_t *keys, uint32_t *vals,
+                        uint32_t *starts, uint32_t *nzones_out, uint32_t *clear, hipStream_t s);
 
 struct SolveArgs {
   const Constraint *con;

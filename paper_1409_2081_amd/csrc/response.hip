@@ -28,6 +28,7 @@
 // order is fixed.  Float32 storage is rounded to nearest afterwards.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "wgsort.hpp"
 
 #pragma clang fp contract(off)
 
@@ -58,6 +59,55 @@ __global__ void k_compact_keys(const uint64_t *__restrict__ keys, const uint32_t
 void launch_compact_keys(const uint64_t *keys, const uint32_t *flags, const uint32_t *pos, int64_t n,
                          uint64_t *out, hipStream_t s) {
   if (n > 0) k_compact_keys<<<grid_for(n, 256), 256, 0, s>>>(keys, flags, pos, n, out);
+}
+
+// The stencil build (keys of up to two hit lists, sort, unique, compaction)
+// for at most 1024 hits in one workgroup; the same keys, order and count as
+// the multi-kernel path.
+__global__ __launch_bounds__(1024) void k_stencils_small(const uint64_t *__restrict__ hk0,
+                                                         const uint32_t *__restrict__ hv0, int n0,
+                                                         const uint64_t *__restrict__ hk1,
+                                                         const uint32_t *__restrict__ hv1, int n1, HitLayout hl,
+                                                         StencilLayout sl, uint64_t *out, uint32_t *total) {
+  __shared__ uint64_t sk[1024];
+  __shared__ uint32_t sv[1024];
+  __shared__ uint32_t wsum[1024 / kWave];
+  const int t = threadIdx.x;
+  const int n = n0 + n1;
+  uint64_t k = ~0ull;
+  uint32_t v = 0;
+  if (t < n) {
+    const uint64_t hk = t < n0 ? hk0[t] : hk1[t - n0];
+    const uint32_t hv = t < n0 ? hv0[t] : hv1[t - n0];
+    const uint64_t f = hk & ((1ull << hl.bits_f) - 1);
+    const uint64_t dir = hk >> (hl.bits_e + hl.bits_f);
+    k = (dir << (sl.bits_v + sl.bits_f)) | ((uint64_t)hv << sl.bits_f) | f;
+  }
+  int P = 2;
+  while (P < n) P <<= 1;
+  wg_bitonic_1k(k, v, P, sk, sv);
+  sk[t] = k;
+  __syncthreads();
+  const bool flag = k != ~0ull && (t == 0 || sk[t - 1] != k);
+  const uint64_t m = __ballot(flag);
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  if (lane == 0) wsum[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t before = 0, count = 0;
+  for (int w = 0; w < 1024 / kWave; ++w) {
+    if (w < wave) before += wsum[w];
+    count += wsum[w];
+  }
+  if (flag) out[before + (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = k;
+  if (t == 0) *total = count;
+}
+
+bool launch_stencils_small(const uint64_t *hk0, const uint32_t *hv0, int64_t n0, const uint64_t *hk1,
+                           const uint32_t *hv1, int64_t n1, HitLayout hl, StencilLayout sl, uint64_t *out,
+                           uint32_t *total, hipStream_t s) {
+  if (n0 + n1 <= 0 || n0 + n1 > 1024) return false;
+  k_stencils_small<<<1, 1024, 0, s>>>(hk0, hv0, (int)n0, hk1, hv1, (int)n1, hl, sl, out, total);
+  return true;
 }
 
 __global__ void k_write_stencils(const uint64_t *__restrict__ keys, int64_t n, StencilLayout sl, int32_t *out) {
@@ -231,6 +281,94 @@ void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, u
   if (S <= 0) return;
   k_zone_starts<<<grid_for(S, 256), 256, 0, s>>>(flags, pos, S, starts, nz);
   k_zone_maxk<<<64, 256, 0, s>>>(starts, nz, maxk);
+}
+
+// The whole zone stage for at most kZonesSmall stencils in one workgroup:
+// the same union-find (only the stencils' vertices are reset), keys (root,
+// stencil), sorting network, segment flags and starts as the multi-kernel
+// path, so every output is identical.  clear[0] receives the largest zone,
+// clear[1] (the solve's retry counter) is zeroed.
+constexpr int kZonesSmall = 1024;
+
+__global__ __launch_bounds__(1024) void k_zones_small(const Constraint *__restrict__ con, int S, int *parent,
+                                                      int bits_s, uint64_t *keys, uint32_t *vals,
+                                                      uint32_t *starts, uint32_t *nz, uint32_t *clear) {
+  __shared__ uint64_t sk[1024];
+  __shared__ uint32_t sv[1024];
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t sst[1024 + 1];
+  const int t = threadIdx.x;
+  const bool act = t < S;
+  const int4 v = act ? con[t].v : make_int4(0, 0, 0, 0);
+  if (act) {
+    parent[v.x] = v.x;
+    parent[v.y] = v.y;
+    parent[v.z] = v.z;
+    parent[v.w] = v.w;
+  }
+  __syncthreads();
+  if (act) {
+    uf_unite(parent, v.x, v.y);
+    uf_unite(parent, v.x, v.z);
+    uf_unite(parent, v.x, v.w);
+  }
+  __syncthreads();
+  uint64_t k = ~0ull;
+  uint32_t val = 0;
+  if (act) {
+    k = ((uint64_t)uf_find(parent, v.x) << bits_s) | (uint64_t)t;
+    val = (uint32_t)t;
+  }
+  int P = 2;
+  while (P < S) P <<= 1;
+  wg_bitonic_1k(k, val, P, sk, sv);
+  if (act) {
+    keys[t] = k;
+    vals[t] = val;
+  }
+  // segment flags and their exclusive prefix (ballots per wavefront)
+  sk[t] = k;
+  __syncthreads();
+  const bool flag = act && (t == 0 || (k >> bits_s) != (sk[t - 1] >> bits_s));
+  const uint64_t m = __ballot(flag);
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  if (lane == 0) wsum[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int w = 0; w < 1024 / kWave; ++w) {
+    if (w < wave) before += wsum[w];
+    total += wsum[w];
+  }
+  const uint32_t pos = before + (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull));
+  if (flag) {
+    starts[pos] = (uint32_t)t;
+    sst[pos] = (uint32_t)t;
+  }
+  if (t == 0) {
+    starts[total] = (uint32_t)S;
+    sst[total] = (uint32_t)S;
+    *nz = total;
+  }
+  __syncthreads();
+  // largest zone
+  uint32_t kz = flag ? sst[pos + 1] - (uint32_t)t : 0u;
+  for (int off = 32; off > 0; off >>= 1) kz = max(kz, (uint32_t)__shfl_xor((int)kz, off));
+  __syncthreads();
+  if (lane == 0) wsum[wave] = kz;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t mk = 0;
+    for (int w = 0; w < 1024 / kWave; ++w) mk = max(mk, wsum[w]);
+    clear[0] = mk;
+    clear[1] = 0u;
+  }
+}
+
+bool launch_zones_small(const Constraint *con, int64_t S, int *parent, int bits_s, uint64_t *keys, uint32_t *vals,
+                        uint32_t *starts, uint32_t *nz, uint32_t *clear, hipStream_t s) {
+  if (S <= 0 || S > kZonesSmall) return false;
+  k_zones_small<<<1, 1024, 0, s>>>(con, (int)S, parent, bits_s, keys, vals, starts, nz, clear);
+  return true;
 }
 
 // -------------------------------------------------------------- zone solve

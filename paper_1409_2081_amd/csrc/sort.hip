@@ -1,14 +1,16 @@
 // Device-wide sort and scan primitives.
 //
 // * Short inputs (n <= kSmallSort) are sorted by one workgroup with a
-//   bitonic network in LDS (keys must then be unique for a stable result;
-//   every caller builds unique keys).
+//   bitonic network (keys must then be unique for a stable result; every
+//   caller builds unique keys): up to 1024 in registers and lane shuffles,
+//   otherwise in LDS.
 // * Longer inputs use an LSD radix sort with 8-bit digits: a per-tile digit
 //   histogram, one scan over all (digit, tile) counts, then a stable scatter
 //   in which each key's rank among equal digits of its wavefront comes from
 //   eight ballots (one per digit bit) and a popcount, and the wavefronts of
 //   a tile are combined through LDS counters.
 #include "common.hpp"
+#include "wgsort.hpp"
 
 namespace hfcr {
 
@@ -54,45 +56,14 @@ __global__ __launch_bounds__(1024) void k_bitonic(uint64_t *keys, uint32_t *vals
   }
 }
 
-// Up to 1024 pairs: thread t holds element t in registers.  The same
-// compare-exchange network as k_bitonic; exchanges between elements less
-// than a wavefront apart use lane shuffles, longer ones go through LDS.
-__device__ inline uint64_t shfl_xor_u64(uint64_t x, int m) {
-  const int lo = __shfl_xor((int)(uint32_t)x, m), hi = __shfl_xor((int)(uint32_t)(x >> 32), m);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
+// Up to 1024 pairs: thread t holds element t in registers (wg_bitonic_1k).
 __global__ __launch_bounds__(1024) void k_bitonic_1k(uint64_t *keys, uint32_t *vals, int n, int P) {
   __shared__ uint64_t sk[1024];
   __shared__ uint32_t sv[1024];
   const int t = threadIdx.x;
   uint64_t k = t < n ? keys[t] : ~0ull;
   uint32_t v = (vals && t < n) ? vals[t] : 0u;
-  for (int size = 2; size <= P; size <<= 1) {
-    const bool up = (t & size) == 0;  // direction of t's bitonic block
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      uint64_t k2;
-      uint32_t v2;
-      if (stride >= kWave) {
-        __syncthreads();
-        sk[t] = k;
-        sv[t] = v;
-        __syncthreads();
-        k2 = sk[t ^ stride];
-        v2 = sv[t ^ stride];
-      } else {
-        k2 = shfl_xor_u64(k, stride);
-        v2 = (uint32_t)__shfl_xor((int)v, stride);
-      }
-      // pair (i, j = i + stride): swap when (key_i > key_j) == up
-      const bool lower = (t & stride) == 0;
-      const bool swap = lower ? ((k > k2) == up) : ((k2 > k) == up);
-      if (swap) {
-        k = k2;
-        v = v2;
-      }
-    }
-  }
+  wg_bitonic_1k(k, v, P, sk, sv);
   if (t < n) {
     keys[t] = k;
     if (vals) vals[t] = v;
