@@ -496,11 +496,13 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
   }
   {
     Scope t(c, 7);
-    ensure(c->inc_keys, 4 * S * sizeof(uint64_t));
-    launch_incidence(ptr<Constraint>(c->con), S, bits_s, ptr<uint64_t>(c->inc_keys), c->s);
-    sort_inplace(c, ptr<uint64_t>(c->inc_keys), nullptr, 4 * S, bits_s + 2 + bits_for(nvt));
-    launch_update(ptr<uint64_t>(c->inc_keys), 4 * S, bits_s, ptr<Constraint>(c->con), ptr<double>(c->lambda),
-                  P.m[0], P.m[1], c->s);
+    if (!launch_update_small(ptr<Constraint>(c->con), S, bits_s, ptr<double>(c->lambda), P.m[0], P.m[1], c->s)) {
+      ensure(c->inc_keys, 4 * S * sizeof(uint64_t));
+      launch_incidence(ptr<Constraint>(c->con), S, bits_s, ptr<uint64_t>(c->inc_keys), c->s);
+      sort_inplace(c, ptr<uint64_t>(c->inc_keys), nullptr, 4 * S, bits_s + 2 + bits_for(nvt));
+      launch_update(ptr<uint64_t>(c->inc_keys), 4 * S, bits_s, ptr<Constraint>(c->con), ptr<double>(c->lambda),
+                    P.m[0], P.m[1], c->s);
+    }
   }
   P.dirty[0] = P.dirty[1] = true;
   if (st) st->max_zone = std::max(st->max_zone, info.maxk);

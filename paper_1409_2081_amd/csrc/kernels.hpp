@@ -116,6 +116,10 @@ size_t solve_slot_doubles(int maxk);  // scratch doubles per workgroup slot
 void launch_incidence(const Constraint *con, int64_t S, int bits_s, uint64_t *keys, hipStream_t s);
 void launch_update(const uint64_t *keys, int64_t n, int bits_s, const Constraint *con, const double *lambda,
                    MeshDev &A, MeshDev &B, hipStream_t s);
+// launch_incidence, the sort and launch_update in one launch for S <= 256
+// stencils; returns false (and launches nothing) otherwise.
+bool launch_update_small(const Constraint *con, int64_t S, int bits_s, const double *lambda, MeshDev &A,
+                         MeshDev &B, hipStream_t s);
 void launch_write_positions(const MeshDev &m, void *out, hipStream_t s);
 
 }  // namespace hfcr

@@ -1105,6 +1105,74 @@ void launch_update(const uint64_t *keys, int64_t n, int bits_s, const Constraint
   k_update<<<grid_for(n, 256), 256, 0, s>>>(keys, n, bits_s, con, lambda, a, b);
 }
 
+// Incidence keys, sort and update for at most 256 stencils (1024
+// incidences) in one workgroup; the same keys, order and sums as
+// k_incidence, the sort and k_update.
+__global__ __launch_bounds__(1024) void k_update_small(const Constraint *__restrict__ con, int S, int bits_s,
+                                                       const double *__restrict__ lambda, MeshOut A, MeshOut B) {
+  __shared__ uint64_t sk[1024];
+  __shared__ uint32_t sv[1024];
+  const int t = threadIdx.x;
+  const int n = 4 * S;
+  const int shift = bits_s + 2;
+  uint64_t k = ~0ull;
+  uint32_t unused = 0;
+  if (t < n) {
+    const int4 v = con[t >> 2].v;
+    const int slot = t & 3;
+    const int vert = slot == 0 ? v.x : slot == 1 ? v.y : slot == 2 ? v.z : v.w;
+    k = ((uint64_t)vert << shift) | (uint64_t)t;
+  }
+  int P = 2;
+  while (P < n) P <<= 1;
+  wg_bitonic_1k(k, unused, P, sk, sv);
+  sk[t] = k;
+  __syncthreads();
+  if (t >= n) return;
+  const uint64_t vtx = k >> shift;
+  if (t > 0 && (sk[t - 1] >> shift) == vtx) return;  // not the first incidence of this vertex
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int j = t; j < n && (sk[j] >> shift) == vtx; ++j) {
+    const uint64_t low = sk[j] & ((1ull << shift) - 1);
+    const int64_t s = (int64_t)(low >> 2);
+    const int slot = (int)(low & 3);
+    const double c = slot == 0 ? 1.0 : -1.0 / 3.0;
+    const double4 nn = con[s].n;
+    const double g = c * lambda[s];
+    sx += g * nn.x;
+    sy += g * nn.y;
+    sz += g * nn.z;
+  }
+  const bool in_a = (int64_t)vtx < A.nv;
+  MeshOut &M = in_a ? A : B;
+  const int lv = in_a ? (int)vtx : (int)(vtx - A.nv);
+  const double w = M.w ? M.w[lv] : 1.0;
+  double x = M.x64[lv] - w * sx;
+  double y = M.x64[(int64_t)M.nv + lv] - w * sy;
+  double z = M.x64[2 * (int64_t)M.nv + lv] - w * sz;
+  if (M.x32) {
+    const float fx = (float)x, fy = (float)y, fz = (float)z;
+    M.x32[lv] = fx;
+    M.x32[(int64_t)M.nv + lv] = fy;
+    M.x32[2 * (int64_t)M.nv + lv] = fz;
+    x = fx;
+    y = fy;
+    z = fz;
+  }
+  M.x64[lv] = x;
+  M.x64[(int64_t)M.nv + lv] = y;
+  M.x64[2 * (int64_t)M.nv + lv] = z;
+}
+
+bool launch_update_small(const Constraint *con, int64_t S, int bits_s, const double *lambda, MeshDev &A,
+                         MeshDev &B, hipStream_t s) {
+  if (S <= 0 || 4 * S > 1024) return false;
+  MeshOut a{A.x64, A.f32 ? A.x32 : nullptr, A.nv, A.inv_mass};
+  MeshOut b{B.x64, B.f32 ? B.x32 : nullptr, B.nv, B.inv_mass};
+  k_update_small<<<1, 1024, 0, s>>>(con, (int)S, bits_s, lambda, a, b);
+  return true;
+}
+
 // ---------------------------------------------------------------- output
 template <typename T>
 __global__ void k_write_positions(const double *__restrict__ x64, int nv, T *out) {
