@@ -145,7 +145,7 @@ typedef struct {
   int32_t pivoted_zones;     /* zones solved by the pivoted fallback (a zone
                                 whose unpivoted pivots fell below 1e-6 of
                                 its largest diagonal entry)                 */
-  int32_t max_query_path;    /* most BVH nodes any one query fetched        */
+  int32_t max_query_path;    /* most traversal steps of any wavefront       */
   double stage_ms[HFCR_STAGES];     /* with HFCR_FLAG_TIMING, else 0        */
   int32_t stage_calls[HFCR_STAGES]; /* timed intervals per stage            */
   int32_t round_hits[HFCR_STAT_ROUNDS];

@@ -150,14 +150,30 @@ __device__ inline void flush_candidates(const TravArgs &A, uint2 *stage, int &cn
   cn = 0;
 }
 
+// Deferred subtrees are shared within a wavefront: when a step leaves lanes
+// idle (their queries finished, mostly at the root box) and other lanes
+// defer a child, those children go to a LIFO in LDS with their query's box,
+// and idle lanes take them.  A wavefront's step count then approaches its
+// total node count / 64 plus the depth, instead of its longest query's node
+// count.  Each lane still keeps a private stack (most recent entry in a
+// register) for the rest.
+constexpr int kWaveQueue = 256;  // shared entries per wavefront
+struct TravTask {
+  float lo[3], hi[3];
+  int qi, node;
+};
+
 template <bool F32, bool TIER0, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
   __shared__ int stack[kStack][BLOCK];
   __shared__ uint2 cstage[BLOCK / kWave][kCandStage];
+  __shared__ TravTask wq[BLOCK / kWave][kWaveQueue];
   const int tid = threadIdx.x;
   uint2 *stage = cstage[tid / kWave];
+  TravTask *queue = wq[tid / kWave];
   int cn = 0;  // candidates staged by this wavefront (wave-uniform)
-  const int qi = xcd_contiguous_block((int)blockIdx.x, (int)gridDim.x) * BLOCK + tid;
+  int qn = 0;  // shared entries queued by this wavefront (wave-uniform)
+  int qi = xcd_contiguous_block((int)blockIdx.x, (int)gridDim.x) * BLOCK + tid;
   if (A.warm && A.nt > 1) {
     unsigned acc = warm_l2(A.nodes, (int64_t)(A.nt - 1) * sizeof(BvhNode), 0u);
     acc = warm_l2(A.leaf_tri, (int64_t)A.nt * sizeof(int4), acc);
@@ -167,23 +183,16 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
   }
   const bool valid = qi < A.ne;
   unsigned long long ncand = 0, nvisit = 0;
-  int4 qe = valid ? A.qedges[qi] : make_int4(0, 0, 0, 0);
-  P3f pf{}, qf{};
-  P3d pd{}, qd{};
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   if (valid) {
+    const int4 qe = A.qedges[qi];
     if (F32) {
-      pf = load_f32(A.ex32, A.env, qe.x);
-      qf = load_f32(A.ex32, A.env, qe.y);
-    } else {
-      pd = load_f64(A.ex64, A.env, qe.x);
-      qd = load_f64(A.ex64, A.env, qe.y);
-    }
-    if (F32) {
+      const P3f pf = load_f32(A.ex32, A.env, qe.x), qf = load_f32(A.ex32, A.env, qe.y);
       lo[0] = fminf(pf.x, qf.x); hi[0] = fmaxf(pf.x, qf.x);
       lo[1] = fminf(pf.y, qf.y); hi[1] = fmaxf(pf.y, qf.y);
       lo[2] = fminf(pf.z, qf.z); hi[2] = fmaxf(pf.z, qf.z);
     } else {
+      const P3d pd = load_f64(A.ex64, A.env, qe.x), qd = load_f64(A.ex64, A.env, qe.y);
       lo[0] = __double2float_rd(fmin(pd.x, qd.x)); hi[0] = __double2float_ru(fmax(pd.x, qd.x));
       lo[1] = __double2float_rd(fmin(pd.y, qd.y)); hi[1] = __double2float_ru(fmax(pd.y, qd.y));
       lo[2] = __double2float_rd(fmin(pd.z, qd.z)); hi[2] = __double2float_ru(fmax(pd.z, qd.z));
@@ -195,13 +204,34 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
   int pending_leaf = (alive && A.nt == 1) ? 0 : -1;
   if (A.nt == 1) alive = false;
   int node = 0, sp = 0, top = -1;
-  unsigned path = 0;
+  unsigned steps = 0;
+  const uint64_t lt = lanemask_lt();
   while (true) {
+    // idle lanes take shared entries (most recent first)
+    if (qn > 0) {
+      const uint64_t idle = __ballot(!alive);
+      const int take = min(__popcll(idle), qn);
+      const int rank = __popcll(idle & lt);
+      __builtin_amdgcn_wave_barrier();
+      if (!alive && rank < take) {
+        const TravTask t = queue[qn - 1 - rank];
+        lo[0] = t.lo[0]; lo[1] = t.lo[1]; lo[2] = t.lo[2];
+        hi[0] = t.hi[0]; hi[1] = t.hi[1]; hi[2] = t.hi[2];
+        qi = t.qi;
+        node = t.node;
+        top = -1;
+        sp = 0;
+        alive = true;
+      }
+      __builtin_amdgcn_wave_barrier();
+      qn -= take;
+    }
     int leaf_a = pending_leaf, leaf_b = -1;
     pending_leaf = -1;
+    const bool any_alive = __any(alive);
+    int defer = -1;
     if (alive) {
       ++nvisit;
-      ++path;
       const BvhNode nd = A.nodes[node];
       const bool o0 = box_overlap(lo, hi, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
       const bool o1 = box_overlap(lo, hi, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
@@ -209,18 +239,8 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
       bool i0 = o0 && c0 >= 0, i1 = o1 && c1 >= 0;
       if (o0 && c0 < 0) leaf_a = ~c0;
       if (o1 && c1 < 0) leaf_b = ~c1;
-      // the most recently deferred node stays in a register (top); older
-      // ones spill to the LDS stack, so a pop after a push costs no LDS load
       if (i0 && i1) {
-        if (top >= 0) {
-          if (sp >= kStack) {
-            atomicOr(A.out.overflow, 1);
-            alive = false;
-          } else {
-            stack[sp++][tid] = top;
-          }
-        }
-        top = c1;
+        defer = c1;
         node = c0;
       } else if (i0) {
         node = c0;
@@ -233,6 +253,38 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
         alive = false;
       }
     }
+    if (any_alive) ++steps;
+    // deferred children: to the shared LIFO while lanes are idle, else to
+    // the lane's own stack (the most recent one stays in a register)
+    const uint64_t dm = __ballot(defer >= 0);
+    if (dm) {
+      const int idle_now = __popcll(__ballot(!alive));
+      const int give = min(min(__popcll(dm), max(idle_now - qn, 0)), kWaveQueue - qn);
+      const int drank = __popcll(dm & lt);
+      __builtin_amdgcn_wave_barrier();
+      if (defer >= 0) {
+        if (drank < give) {
+          TravTask t;
+          t.lo[0] = lo[0]; t.lo[1] = lo[1]; t.lo[2] = lo[2];
+          t.hi[0] = hi[0]; t.hi[1] = hi[1]; t.hi[2] = hi[2];
+          t.qi = qi;
+          t.node = defer;
+          queue[qn + drank] = t;
+        } else {
+          if (top >= 0) {
+            if (sp >= kStack) {
+              atomicOr(A.out.overflow, 1);
+              alive = false;
+            } else {
+              stack[sp++][tid] = top;
+            }
+          }
+          top = defer;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      qn += give;
+    }
     // stage up to two candidate leaves found at this step
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -241,12 +293,12 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
       if (m == 0) continue;
       if (leaf >= 0) {
         ++ncand;
-        stage[cn + __popcll(m & lanemask_lt())] = make_uint2((uint32_t)qi, (uint32_t)leaf);
+        stage[cn + __popcll(m & lt)] = make_uint2((uint32_t)qi, (uint32_t)leaf);
       }
       cn += __popcll(m);
     }
     if (cn > kCandStage - 2 * kWave) flush_candidates<BLOCK>(A, stage, cn);
-    if (!__any(alive)) break;
+    if (!__any(alive) && qn == 0) break;
   }
   if (cn > 0) flush_candidates<BLOCK>(A, stage, cn);
   // one counter update per wave
@@ -257,9 +309,8 @@ __global__ __launch_bounds__(BLOCK) void k_traverse(TravArgs A) {
   if (__lane_id() == 0) {
     if (ncand) atomicAdd(A.out.cand, ncand);
     if (nvisit) atomicAdd(A.out.visits, nvisit);
+    if (steps) atomicMax(A.out.max_path, steps);
   }
-  for (int off = 32; off > 0; off >>= 1) path = max(path, (unsigned)__shfl_xor((int)path, off));
-  if (__lane_id() == 0 && path) atomicMax(A.out.max_path, path);
 }
 
 static TravArgs make_args(const MeshDev &E, const MeshDev &F, int dir, HitLayout lay, const DcdOut &out) {

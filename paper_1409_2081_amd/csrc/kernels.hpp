@@ -37,7 +37,7 @@ struct DcdOut {
   unsigned long long *f32_unsure;
   unsigned long long *exact;    // exact-tier tests
   unsigned long long *visits;   // BVH nodes fetched
-  unsigned *max_path;           // longest single-query node count
+  unsigned *max_path;           // most traversal steps of any wavefront
   int *overflow;         // traversal stack overflow flag
   int warm;              // warm the L2 before traversing
   uint2 *cand_buf;       // (query index, leaf index) pairs found by the traversal
