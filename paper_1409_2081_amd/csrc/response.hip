@@ -495,56 +495,58 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
   if (tid == 0) *flag = 0;
   __syncthreads();
   const double thr_u = 1e-6 * dmax;
+  // (1) diagonal tile J and the forward substitution of its block: lane r < 8
+  // of wave 0 holds row r of the tile, its rhs entry, y_r and 1/L_rr.
+  // Column by column: the pivot is read from its lane, the column scaled and
+  // the trailing lower part updated, each value computed as the serial
+  // column-oriented algorithm computes it.  Values move between lanes by
+  // lane reads (scalar registers), not through LDS.  Called by wave 0 only.
+  auto factor_diag = [&](int J) {
+    double *D = M + tile_off(J, J);
+    const int r = tid;
+    double row[TB];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) row[c] = (r < TB && r >= c) ? D[sw(r, c)] : 0.0;
+    double rb = r < TB ? rhs[J * TB + r] : 0.0, yv = 0.0, dv = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < TB; ++c) {
+      const double piv = read_lane(row[c], c);
+      bad = bad || !(piv > thr_u);
+      const double l = sqrt(fmax(piv, 0.0)), inv = 1.0 / l;
+      if (r > c) row[c] = row[c] * inv;
+      if (r == c) row[c] = l;
+#pragma unroll
+      for (int cc = c + 1; cc < TB; ++cc) {
+        const double lcc = read_lane(row[c], cc);  // L[cc][c]
+        if (r >= cc) row[cc] = row[cc] - row[c] * lcc;
+      }
+      // forward substitution of the block's rhs
+      const double yc = read_lane(rb, c) * inv;
+      if (r == c) {
+        yv = yc;
+        dv = inv;
+      }
+      if (r < TB && r > c) rb = rb - row[c] * yc;
+    }
+    if (bad) {
+      if (tid == 0) *flag = 1;
+    } else if (r < TB) {
+#pragma unroll
+      for (int c = 0; c < TB; ++c)
+        if (c <= r) {
+          D[sw(r, c)] = row[c];
+          if (STAGE) P[sw(r, c)] = row[c];
+        }
+      y[J * TB + r] = yv;
+      dinv[J * TB + r] = dv;
+    }
+  };
+  if (tid < kWave) factor_diag(0);
+  __syncthreads();
+  if (*flag) return false;
   for (int J = 0; J < T; ++J) {
     double *D = M + tile_off(J, J);
-    // (1) diagonal tile and the forward substitution of its block: lane r < 8
-    // of wave 0 holds row r of the tile, its rhs entry, y_r and 1/L_rr.
-    // Column by column: the pivot is read from its lane, the column scaled
-    // and the trailing lower part updated, each value computed as the serial
-    // column-oriented algorithm computes it.  Values move between lanes by
-    // lane reads (scalar registers), not through LDS.
-    if (tid < kWave) {
-      const int r = tid;
-      double row[TB];
-#pragma unroll
-      for (int c = 0; c < TB; ++c) row[c] = (r < TB && r >= c) ? D[sw(r, c)] : 0.0;
-      double rb = r < TB ? rhs[J * TB + r] : 0.0, yv = 0.0, dv = 0.0;
-      bool bad = false;
-#pragma unroll
-      for (int c = 0; c < TB; ++c) {
-        const double piv = read_lane(row[c], c);
-        bad = bad || !(piv > thr_u);
-        const double l = sqrt(fmax(piv, 0.0)), inv = 1.0 / l;
-        if (r > c) row[c] = row[c] * inv;
-        if (r == c) row[c] = l;
-#pragma unroll
-        for (int cc = c + 1; cc < TB; ++cc) {
-          const double lcc = read_lane(row[c], cc);  // L[cc][c]
-          if (r >= cc) row[cc] = row[cc] - row[c] * lcc;
-        }
-        // forward substitution of the block's rhs
-        const double yc = read_lane(rb, c) * inv;
-        if (r == c) {
-          yv = yc;
-          dv = inv;
-        }
-        if (r < TB && r > c) rb = rb - row[c] * yc;
-      }
-      if (bad) {
-        if (tid == 0) *flag = 1;
-      } else if (r < TB) {
-#pragma unroll
-        for (int c = 0; c < TB; ++c)
-          if (c <= r) {
-            D[sw(r, c)] = row[c];
-            if (STAGE) P[sw(r, c)] = row[c];
-          }
-        y[J * TB + r] = yv;
-        dinv[J * TB + r] = dv;
-      }
-    }
-    __syncthreads();
-    if (*flag) return false;
     // (2) panel: L_IJ = A_IJ L_JJ^-T, and the forward-substitution update
     for (int it = tid; it < (T - J - 1) * TB; it += BLOCK) {
       const int I = J + 1 + it / TB, r = it % TB;
@@ -572,13 +574,17 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
     __syncthreads();
     // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I, one
     // wavefront per tile pair, lane 8r + c computing element (r, c) (the
-    // rows of L_IJ and L_KJ it reads are each shared by eight lanes)
+    // rows of L_IJ and L_KJ it reads are each shared by eight lanes).
+    // Look-ahead: wave 0 updates only tile (J+1, J+1) and then factors it,
+    // while the other wavefronts update the rest, so the serial diagonal
+    // factorization overlaps the trailing update.
     {
       const int nrem = T - J - 1;
       const int npair = nrem * (nrem + 1) / 2;
       const int r = (tid & 63) >> 3, c = tid & 7;
+      const int wave = tid >> 6;
       int u = 0;  // tile row of this wave's current pair, advanced incrementally
-      for (int p = tid >> 6; p < npair; p += BLOCK / 64) {
+      for (int p = wave; p < (wave == 0 ? min(npair, 1) : npair); p += (wave == 0 ? 1 : BLOCK / 64 - 1)) {
         while ((u + 1) * (u + 2) / 2 <= p) ++u;
         const int v = p - u * (u + 1) / 2;
         const int I = J + 1 + u, K = J + 1 + v;
@@ -598,8 +604,13 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
         for (int m = 0; m < TB; ++m) s = s + li[m] * lk[m];
         *C = c0 - s;
       }
+      if (wave == 0 && J + 1 < T) {
+        __threadfence_block();  // this wavefront's update of tile (J+1, J+1) is read by other lanes
+        factor_diag(J + 1);
+      }
     }
     __syncthreads();
+    if (*flag) return false;
   }
   // backward: L^T lambda = y, tile by tile
   for (int J = T - 1; J >= 0; --J) {
