@@ -34,6 +34,7 @@ struct PassCount {
 struct Counters {
   uint32_t err;
   uint32_t maxabs[2];
+  uint32_t tri_diff[2];  // triangle arrays differ from the cached topology's
   int32_t overflow;
   uint32_t total;
   uint32_t nzones;
@@ -70,6 +71,13 @@ struct hfcr_ctx {
   // per mesh
   DBuf x64[2], x32[2], edges[2], qedges[2], leaf_tri[2], nodes[2], leaf_parent[2], counters_n[2], root_box[2],
       codes[2], scene_box[2], topo[2];
+  // topology kept from the previous call (edge sets, query order, BVH tree),
+  // reused while a mesh's triangle array is unchanged
+  struct TopoCache {
+    int nv = -1, nt = -1, ne = 0;
+    bool edges = false, bvh = false;
+  } topo_cache[2];
+  DBuf tri_cache[2];
   // detection
   DBuf hk[2], hv[2], amb[2], cand;
   // generic sort / scan scratch
@@ -244,6 +252,16 @@ void setup_mesh(hfcr_ctx *c, Pair &P, int i, const hfcr_mesh *src, const double 
   launch_ingest(m, &dc->err, &dc->maxabs[i], c->s);
 }
 
+// Points mesh i's edge fields at the context's buffers (sized for ne edges).
+void bind_edges(hfcr_ctx *c, Pair &P, int i, int64_t ne) {
+  MeshDev &m = P.m[i];
+  m.ne = (int)ne;
+  ensure(c->edges[i], std::max<int64_t>(ne, 1) * sizeof(int2));
+  ensure(c->qedges[i], std::max<int64_t>(ne, 1) * sizeof(int4));
+  m.edges = ptr<int2>(c->edges[i]);
+  m.qedges = ptr<int4>(c->qedges[i]);
+}
+
 void build_edges(hfcr_ctx *c, Pair &P, int i) {
   MeshDev &m = P.m[i];
   const int64_t n = 3 * (int64_t)m.nt;
@@ -258,11 +276,7 @@ void build_edges(hfcr_ctx *c, Pair &P, int i) {
   sort_inplace(c, keys, nullptr, n, 32 + bits_for((int64_t)m.nv + 1));
   launch_unique_flags(keys, n, (uint64_t)m.nv << 32, ptr<uint32_t>(c->flags), c->s);
   const uint32_t ne = scan_count(c, ptr<uint32_t>(c->flags), n);
-  m.ne = (int)ne;
-  ensure(c->edges[i], std::max<int64_t>(ne, 1) * sizeof(int2));
-  ensure(c->qedges[i], std::max<int64_t>(ne, 1) * sizeof(int4));
-  m.edges = ptr<int2>(c->edges[i]);
-  m.qedges = ptr<int4>(c->qedges[i]);
+  bind_edges(c, P, i, ne);
   launch_compact_edges(keys, ptr<uint32_t>(c->flags), ptr<uint32_t>(c->pos), n, m.edges, c->s);
   if (ne == 0) return;
   // queries in Morton order of the edge midpoints
@@ -275,7 +289,8 @@ void build_edges(hfcr_ctx *c, Pair &P, int i) {
   P.has_edges[i] = true;
 }
 
-void build_bvh(hfcr_ctx *c, Pair &P, int i) {
+// Points mesh i's BVH fields at the context's buffers.
+void bind_bvh(hfcr_ctx *c, Pair &P, int i) {
   MeshDev &m = P.m[i];
   const int nt = m.nt;
   ensure(c->leaf_tri[i], std::max(nt, 1) * sizeof(int4));
@@ -299,6 +314,12 @@ void build_bvh(hfcr_ctx *c, Pair &P, int i) {
   m.top_list = tb + 3 * n1;
   m.top_pre = tb + 4 * n1;
   m.top_count = tb + 5 * n1;
+}
+
+void build_bvh(hfcr_ctx *c, Pair &P, int i) {
+  MeshDev &m = P.m[i];
+  const int nt = m.nt;
+  bind_bvh(c, P, i);
   if (nt == 0) return;
   launch_bounds(m, ptr<float>(c->scene_box[i]), c->s);
   ensure(c->sk0, (size_t)nt * sizeof(uint64_t));
@@ -569,6 +590,14 @@ void setup_pair(hfcr_ctx *c, Pair &P, const hfcr_mesh *a, const hfcr_mesh *b, in
     Scope t(c, 0);
     setup_mesh(c, P, 0, a, o->inv_mass_a);
     setup_mesh(c, P, 1, b, o->inv_mass_b);
+    Counters *dc = ptr<Counters>(c->ctr);
+    bool cached[2];
+    for (int i = 0; i < 2; ++i) {
+      const hfcr_ctx::TopoCache &tc = c->topo_cache[i];
+      const MeshDev &m = P.m[i];
+      cached[i] = tc.nv == m.nv && tc.nt == m.nt && m.nt > 0 && (tc.edges || tc.bvh);
+      if (cached[i]) launch_tri_diff(m.tri_in, ptr<int32_t>(c->tri_cache[i]), 3 * (int64_t)m.nt, &dc->tri_diff[i], c->s);
+    }
     readback(c);
     if (c->hctr->err & 1u)
       throw StatusError{HFCR_E_INVALID, "non-finite or out-of-domain coordinate (|x| must be 0 or in [2^-200, 2^200])"};
@@ -578,11 +607,51 @@ void setup_pair(hfcr_ctx *c, Pair &P, const hfcr_mesh *a, const hfcr_mesh *b, in
       std::memcpy(&m, &c->hctr->maxabs[i], sizeof(float));
       P.m[i].small_coords = m <= 4294967296.0f;
     }
+    // the edge sets, query orders and BVH trees of the previous call stay
+    // valid while the triangle arrays are unchanged (refitting takes care of
+    // the new positions; the hits do not depend on the tree's shape)
+    bool built[2] = {false, false};
+    for (int i = 0; i < 2; ++i)
+      if (!(cached[i] && c->hctr->tri_diff[i] == 0)) c->topo_cache[i] = hfcr_ctx::TopoCache{};
     for (int q = 0; q < P.ndirs; ++q) {
       const int dir = P.dirs[q];
       const int ei = dir == 0 ? 0 : 1, fi = dir == 0 ? 1 : 0;
-      if (!P.has_edges[ei]) build_edges(c, P, ei);
-      if (!P.has_bvh[fi]) build_bvh(c, P, fi);
+      if (!P.has_edges[ei]) {
+        if (c->topo_cache[ei].edges) {
+          bind_edges(c, P, ei, c->topo_cache[ei].ne);
+          P.has_edges[ei] = true;
+        } else {
+          build_edges(c, P, ei);
+          built[ei] = true;
+          P.has_edges[ei] = true;
+        }
+      }
+      if (!P.has_bvh[fi]) {
+        if (c->topo_cache[fi].bvh) {
+          bind_bvh(c, P, fi);
+          P.has_bvh[fi] = true;
+          P.dirty[fi] = true;
+        } else {
+          build_bvh(c, P, fi);
+          built[fi] = true;
+        }
+      }
+    }
+    for (int i = 0; i < 2; ++i) {
+      if (!built[i]) continue;
+      hfcr_ctx::TopoCache &tc = c->topo_cache[i];
+      if (tc.nt != P.m[i].nt || tc.nv != P.m[i].nv) {  // new content: keep a copy of the triangles
+        ensure(c->tri_cache[i], std::max<int64_t>(3 * (int64_t)P.m[i].nt, 1) * sizeof(int32_t));
+        HIP_CHECK(hipMemcpyAsync(c->tri_cache[i].p, P.m[i].tri_in, 3 * (size_t)P.m[i].nt * sizeof(int32_t),
+                                 hipMemcpyDeviceToDevice, c->s));
+      }
+      tc.nv = P.m[i].nv;
+      tc.nt = P.m[i].nt;
+      if (P.has_edges[i]) {  // built or bound in this call; else keep what the cache holds
+        tc.ne = P.m[i].ne;
+        tc.edges = true;
+      }
+      tc.bvh = tc.bvh || P.has_bvh[i];
     }
   }
   int64_t maxe = std::max(P.m[0].ne, P.m[1].ne), maxf = std::max(P.m[0].nt, P.m[1].nt);
@@ -687,7 +756,7 @@ void hfcr_destroy(hfcr_ctx *c) {
   for (int i = 0; i < 2; ++i) {
     DBuf *m[] = {&c->x64[i], &c->x32[i], &c->edges[i], &c->qedges[i], &c->leaf_tri[i], &c->nodes[i],
                  &c->leaf_parent[i], &c->counters_n[i], &c->root_box[i], &c->codes[i], &c->scene_box[i], &c->topo[i],
-                 &c->hk[i], &c->hv[i], &c->amb[i]};
+                 &c->hk[i], &c->hv[i], &c->amb[i], &c->tri_cache[i]};
     for (DBuf *b : m)
       if (b->p) (void)hipFree(b->p);
   }

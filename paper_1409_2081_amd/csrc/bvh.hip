@@ -52,6 +52,17 @@ __global__ void k_check_tri(const int32_t *__restrict__ tri, int nt, int nv, uns
   }
 }
 
+// *diff |= 1 when the two index arrays differ anywhere.
+__global__ void k_tri_diff(const int32_t *__restrict__ a, const int32_t *__restrict__ b, int64_t n, unsigned *diff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool d = i < n && a[i] != b[i];
+  if (__any(d) && __lane_id() == 0) atomicOr(diff, 1u);
+}
+
+void launch_tri_diff(const int32_t *a, const int32_t *b, int64_t n, unsigned *diff, hipStream_t s) {
+  if (n > 0) k_tri_diff<<<grid_for(n, 256), 256, 0, s>>>(a, b, n, diff);
+}
+
 void launch_ingest(const MeshDev &m, unsigned *err, unsigned *maxabs, hipStream_t s) {
   if (m.nv > 0) {
     if (m.f32)

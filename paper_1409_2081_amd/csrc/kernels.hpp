@@ -7,6 +7,8 @@ namespace hfcr {
 
 // bvh.hip
 void launch_ingest(const MeshDev &m, unsigned *err, unsigned *maxabs, hipStream_t s);
+// *diff |= 1 when the index arrays a[0..n) and b[0..n) differ.
+void launch_tri_diff(const int32_t *a, const int32_t *b, int64_t n, unsigned *diff, hipStream_t s);
 void launch_edge_keys(const MeshDev &m, uint64_t *keys, hipStream_t s);
 void launch_unique_flags(const uint64_t *keys, int64_t n, uint64_t invalid_from, uint32_t *flags,
                          hipStream_t s);

@@ -8,6 +8,8 @@ storage.  Multi-round comparisons run in lockstep: every round starts both
 sides from the same positions, because a one-ulp difference can change a
 later round's hit set legitimately.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -226,6 +228,32 @@ def test_inverse_masses_pinned_face_mesh(hfcr_ctx):
     assert g["stats"]["rounds"] == o["rounds"] and o["converged"]
     np.testing.assert_array_equal(_np(g["pos_b"]), pair.pos_b)
     assert np.abs(_np(g["pos_a"]) - o["pos_a"]).max() <= 1e-6 * _diag(pair)
+
+
+def test_topology_reuse_does_not_change_results():
+    # a context keeps the edge sets and BVH trees of its last call and reuses
+    # them while the triangle arrays are unchanged; results must equal those
+    # of a fresh context, also for new positions on the same triangles and
+    # for orientations that need structures the last call did not build
+    warm, fresh = hf.Context(0), hf.Context(0)
+    base = meshgen.sphere_sheet(z=0.6)
+    moved = dataclasses.replace(base, pos_a=base.pos_a + np.array([0.0, 0.0, 0.1]), pos_b=base.pos_b.copy())
+    seq = [(base, meshgen.ORIENT_B), (base, meshgen.ORIENT_B), (moved, meshgen.ORIENT_B), (moved, meshgen.ORIENT_A),
+           (moved, meshgen.ORIENT_BOTH), (meshgen.linked_tori(nu=32, nv=16, shift=1.5), meshgen.ORIENT_BOTH),
+           (base, meshgen.ORIENT_BOTH)]
+    for pair, orient in seq:
+        args = (*hf.pair_tensors(pair), orient, pair.d)
+        g = warm.resolve(*args, tier=1, max_rounds=4)
+        f = fresh.resolve(*args, tier=1, max_rounds=4)
+        fresh.close()
+        fresh = hf.Context(0)
+        assert g["status"] == f["status"], (pair.name, orient)
+        for k in ("pos_a", "pos_b", "hits", "stencils"):
+            assert torch.equal(g[k], f[k]), (pair.name, orient, k)
+        for k in ("rounds", "hits0", "stencils0", "candidates", "residual_hits", "round_hits", "round_stencils"):
+            assert g["stats"][k] == f["stats"][k], (pair.name, orient, k)
+    warm.close()
+    fresh.close()
 
 
 def test_deterministic_bitwise(hfcr_ctx):
