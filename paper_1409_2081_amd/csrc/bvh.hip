@@ -481,37 +481,64 @@ __device__ inline void node_union(const BvhNode &nd, float lo[3], float hi[3]) {
   hi[0] = fmaxf(nd.a.w, nd.c.y); hi[1] = fmaxf(nd.b.x, nd.c.z); hi[2] = fmaxf(nd.b.y, nd.c.w);
 }
 
+// One workgroup per chunk of kChunk leaves.  The chunk's internal nodes
+// (indices base .. base + kChunk - 1) keep a copy of their child boxes,
+// parent and top flag in LDS, so a climb step is LDS work: the second thread
+// to arrive at a node reads its sibling's box there.  Every child box is
+// also stored to the node array, which the traversal reads; a climb stops
+// at a top node (handled by k_refit_top).
 template <bool F32>
 __global__ __launch_bounds__(kChunk) void k_refit_chunk(const int4 *__restrict__ leaf_tri, int nt,
                                                         const double *__restrict__ x64, const float *__restrict__ x32,
                                                         int nv, BvhNode *nodes, const int *__restrict__ leaf_parent,
                                                         const int *__restrict__ top_pos, float *root_box) {
   __shared__ int cnt[kChunk];
+  __shared__ float sbox[kChunk][12];  // child boxes, in the node array's layout
+  __shared__ int spar[kChunk];        // parent << 1 | slot, or -1 at the root
+  __shared__ unsigned char stop[kChunk];
   const int base = blockIdx.x * kChunk;
-  cnt[threadIdx.x] = 0;
+  const int tid = threadIdx.x;
+  cnt[tid] = 0;
+  {
+    const int n = base + tid;
+    if (n < nt - 1) {
+      const int4 d = nodes[n].d;
+      spar[tid] = d.z < 0 ? -1 : (d.z << 1) | d.w;
+      stop[tid] = top_pos[n] >= 0;
+    }
+  }
   __syncthreads();
-  const int l = base + threadIdx.x;
+  const int l = base + tid;
   if (l >= nt) return;
   float lo[3], hi[3];
   leaf_box(leaf_tri[l], F32, x64, x32, nv, lo, hi);
-  const int pp = leaf_parent[l];
-  int node = pp >> 1;
-  store_child_box(&nodes[node], pp & 1, lo, hi);
-  while (top_pos[node] < 0) {
-    const int old = __hip_atomic_fetch_add(&cnt[node - base], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+  int pp = leaf_parent[l];
+  while (true) {
+    const int node = pp >> 1, slot = pp & 1;
+    store_child_box(&nodes[node], slot, lo, hi);
+    // a node outside the chunk's index range has a range that crosses it
+    const int li = node - base;
+    if (li < 0 || li >= kChunk || stop[li]) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      sbox[li][6 * slot + k] = lo[k];
+      sbox[li][6 * slot + 3 + k] = hi[k];
+    }
+    const int old = __hip_atomic_fetch_add(&cnt[li], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (old == 0) return;
-    const BvhNode nd = nodes[node];
-    node_union(nd, lo, hi);
-    const int parent = nd.d.z;
-    if (parent < 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(sbox[li][k], sbox[li][6 + k]);
+      hi[k] = fmaxf(sbox[li][3 + k], sbox[li][9 + k]);
+    }
+    pp = spar[li];
+    if (pp < 0) {
       for (int k = 0; k < 3; ++k) {
         root_box[k] = lo[k];
         root_box[3 + k] = hi[k];
       }
       return;
     }
-    store_child_box(&nodes[parent], nd.d.w, lo, hi);
-    node = parent;
   }
 }
 
