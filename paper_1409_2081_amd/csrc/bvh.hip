@@ -543,12 +543,64 @@ __global__ __launch_bounds__(kChunk) void k_refit_chunk(const int4 *__restrict__
 }
 
 constexpr int kTopLds = 32 * 1024;  // top nodes handled by the two-phase refit
+constexpr int kTopStage = 1536;     // top nodes whose boxes fit in LDS (56 B each)
 
+// The nodes whose range crosses a chunk boundary, climbed by one workgroup.
+// With at most `cap` of them, their child boxes, parents and arrival
+// counters live in LDS (staged from the node array, which the chunk kernel
+// has just written), so a climb step is LDS work; otherwise the boxes are
+// read from the node array.  Every child box is also stored to the array.
 __global__ __launch_bounds__(1024) void k_refit_top(BvhNode *nodes, const int *__restrict__ top_pos,
                                                     const int *__restrict__ top_list, const int *__restrict__ top_pre,
-                                                    const int *__restrict__ top_count, float *root_box) {
-  extern __shared__ int tcnt[];
+                                                    const int *__restrict__ top_count, float *root_box, int cap) {
+  extern __shared__ int dyn[];
   const int ntop = *top_count;
+  if (ntop <= cap) {
+    float *tbox = reinterpret_cast<float *>(dyn);  // [cap][12]
+    int *tpar = dyn + 12 * cap;                    // parent's top index << 1 | slot, or -1 at the root
+    int *tcnt = tpar + cap;
+    for (int t = threadIdx.x; t < ntop; t += 1024) {
+      const BvhNode nd = nodes[top_list[t]];
+      const float *f = reinterpret_cast<const float *>(&nd);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) tbox[12 * t + k] = f[k];
+      tpar[t] = nd.d.z < 0 ? -1 : (top_pos[nd.d.z] << 1) | nd.d.w;
+      tcnt[t] = top_pre[t];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntop; t += 1024) {
+      if (top_pre[t] != 2) continue;  // a climb starts where both children are done
+      int u = t;
+      while (true) {
+        float lo[3], hi[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = fminf(tbox[12 * u + k], tbox[12 * u + 6 + k]);
+          hi[k] = fmaxf(tbox[12 * u + 3 + k], tbox[12 * u + 9 + k]);
+        }
+        const int pt = tpar[u];
+        if (pt < 0) {
+          for (int k = 0; k < 3; ++k) {
+            root_box[k] = lo[k];
+            root_box[3 + k] = hi[k];
+          }
+          break;
+        }
+        const int pu = pt >> 1, slot = pt & 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          tbox[12 * pu + 6 * slot + k] = lo[k];
+          tbox[12 * pu + 6 * slot + 3 + k] = hi[k];
+        }
+        store_child_box(&nodes[top_list[pu]], slot, lo, hi);
+        const int old = __hip_atomic_fetch_add(&tcnt[pu], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old != 1) break;  // the other child is not finished yet
+        u = pu;
+      }
+    }
+    return;
+  }
+  int *tcnt = dyn;
   for (int t = threadIdx.x; t < ntop; t += 1024) tcnt[t] = top_pre[t];
   __syncthreads();
   for (int t = threadIdx.x; t < ntop; t += 1024) {
@@ -592,8 +644,11 @@ void launch_refit(const MeshDev &m, hipStream_t s) {
         return true;
       }();
       (void)attr_set;
-      const size_t bytes = (size_t)std::min<int64_t>((int64_t)nchunks * 64, m.nt) * sizeof(int);
-      k_refit_top<<<1, 1024, bytes, s>>>(m.nodes, m.top_pos, m.top_list, m.top_pre, m.top_count, m.root_box);
+      // at most nchunks * 64 top nodes; the LDS staging takes up to kTopStage of them
+      const int64_t maxtop = std::min<int64_t>((int64_t)nchunks * 64, m.nt);
+      const int cap = (int)std::min<int64_t>(maxtop, kTopStage);
+      const size_t bytes = std::max<size_t>((size_t)maxtop * sizeof(int), (size_t)cap * 14 * sizeof(int));
+      k_refit_top<<<1, 1024, bytes, s>>>(m.nodes, m.top_pos, m.top_list, m.top_pre, m.top_count, m.root_box, cap);
     }
     return;
   }
