@@ -333,10 +333,9 @@ void build_bvh(hfcr_ctx *c, Pair &P, int i) {
 
 void reset_counters(hfcr_ctx *c) { HIP_CHECK(hipMemsetAsync(c->ctr.p, 0, sizeof(Counters), c->s)); }
 
-// One detection pass in direction dir; leaves the hits in hk/hv[dir], sorted
-// when `sorted` (the order only matters for the returned round-0 list: the
-// stencils built from later rounds are sorted and made unique anyway).
-int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
+// Launches one detection pass in direction dir (refitting the face side's
+// tree first if its positions changed); the counts are read back later.
+void detect_launch(hfcr_ctx *c, Pair &P, int dir) {
   const int ei = dir == 0 ? 0 : 1, fi = dir == 0 ? 1 : 0;
   MeshDev &E = P.m[ei], &F = P.m[fi];
   if (P.dirty[fi]) {
@@ -345,65 +344,124 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
     P.dirty[fi] = false;
   }
   Counters *dc = ptr<Counters>(c->ctr);
+  ensure(c->hk[dir], P.hit_cap[dir] * sizeof(uint64_t));
+  ensure(c->hv[dir], P.hit_cap[dir] * sizeof(uint32_t));
+  ensure(c->amb[dir], P.amb_cap[dir] * sizeof(uint2));
+  ensure(c->cand, P.cand_cap[dir] * sizeof(uint2));
+  // use all of what earlier calls allocated
+  P.hit_cap[dir] = std::max<int64_t>(P.hit_cap[dir], (int64_t)std::min(c->hk[dir].bytes / sizeof(uint64_t),
+                                                                       c->hv[dir].bytes / sizeof(uint32_t)));
+  P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], (int64_t)(c->amb[dir].bytes / sizeof(uint2)));
+  P.cand_cap[dir] = std::max<int64_t>(P.cand_cap[dir], (int64_t)(c->cand.bytes / sizeof(uint2)));
+  PassCount *pc = &dc->pass[dir];
+  HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(PassCount), c->s));
+  DcdOut out;
+  out.keys = ptr<uint64_t>(c->hk[dir]);
+  out.vals = ptr<uint32_t>(c->hv[dir]);
+  out.count = &pc->hits;
+  out.cap = P.hit_cap[dir];
+  out.amb = ptr<uint2>(c->amb[dir]);
+  out.amb_count = &pc->amb;
+  out.amb_cap = P.amb_cap[dir];
+  out.cand = &pc->cand;
+  out.f32_unsure = &pc->f32_unsure;
+  out.exact = &pc->exact;
+  out.visits = &pc->visits;
+  out.max_path = &dc->max_path;
+  out.overflow = &dc->overflow;
+  out.warm = c->tune.trav_warm;
+  out.cand_buf = ptr<uint2>(c->cand);
+  out.cand_count = &pc->cand_n;
+  out.cand_cap = P.cand_cap[dir];
+  {
+    Scope t(c, 2);
+    launch_traverse(E, F, dir, P.tier0, P.hl, out, c->tune.trav_block, c->s);
+  }
+  {
+    Scope t(c, 3);
+    launch_narrow(E, F, dir, P.tier0, P.hl, out, c->s);
+    launch_exact(E, F, dir, P.hl, out, c->s);
+  }
+}
+
+// After the readback that follows detect_launch: whether the pass fit its
+// buffers (then its counts are added to the pair's and its hit count kept);
+// otherwise the capacities grow for a redo.
+bool detect_accept(hfcr_ctx *c, Pair &P, int dir) {
+  if (c->hctr->overflow & 1) throw StatusError{HFCR_E_DEVICE, "BVH traversal stack overflow"};
+  const PassCount &hp = c->hctr->pass[dir];
+  const int64_t nh = hp.hits, na = hp.amb, nc = hp.cand_n;
+  if (nc <= P.cand_cap[dir] && nh <= P.hit_cap[dir] && na <= P.amb_cap[dir]) {
+    P.cand += (int64_t)hp.cand;
+    P.f32_unsure += (int64_t)hp.f32_unsure;
+    P.exact += (int64_t)hp.exact;
+    P.visits += (int64_t)hp.visits;
+    P.hits_n[dir] = nh;
+    return true;
+  }
+  P.hit_cap[dir] = std::max<int64_t>(P.hit_cap[dir], nh + nh / 2 + 64);
+  P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], na + na / 2 + 64);
+  P.cand_cap[dir] = std::max<int64_t>(P.cand_cap[dir], nc + nc / 8 + 64);
+  return false;
+}
+
+// One detection pass in direction dir; leaves the hits in hk/hv[dir], sorted
+// when `sorted` (the order only matters for the returned round-0 list: the
+// stencils built from later rounds are sorted and made unique anyway).
+int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
   for (int attempt = 0; attempt < 8; ++attempt) {
-    ensure(c->hk[dir], P.hit_cap[dir] * sizeof(uint64_t));
-    ensure(c->hv[dir], P.hit_cap[dir] * sizeof(uint32_t));
-    ensure(c->amb[dir], P.amb_cap[dir] * sizeof(uint2));
-    ensure(c->cand, P.cand_cap[dir] * sizeof(uint2));
-    // use all of what earlier calls allocated
-    P.hit_cap[dir] = std::max<int64_t>(P.hit_cap[dir], (int64_t)std::min(c->hk[dir].bytes / sizeof(uint64_t),
-                                                                         c->hv[dir].bytes / sizeof(uint32_t)));
-    P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], (int64_t)(c->amb[dir].bytes / sizeof(uint2)));
-    P.cand_cap[dir] = std::max<int64_t>(P.cand_cap[dir], (int64_t)(c->cand.bytes / sizeof(uint2)));
-    PassCount *pc = &dc->pass[dir];
-    HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(PassCount), c->s));
-    DcdOut out;
-    out.keys = ptr<uint64_t>(c->hk[dir]);
-    out.vals = ptr<uint32_t>(c->hv[dir]);
-    out.count = &pc->hits;
-    out.cap = P.hit_cap[dir];
-    out.amb = ptr<uint2>(c->amb[dir]);
-    out.amb_count = &pc->amb;
-    out.amb_cap = P.amb_cap[dir];
-    out.cand = &pc->cand;
-    out.f32_unsure = &pc->f32_unsure;
-    out.exact = &pc->exact;
-    out.visits = &pc->visits;
-    out.max_path = &dc->max_path;
-    out.overflow = &dc->overflow;
-    out.warm = c->tune.trav_warm;
-    out.cand_buf = ptr<uint2>(c->cand);
-    out.cand_count = &pc->cand_n;
-    out.cand_cap = P.cand_cap[dir];
-    {
-      Scope t(c, 2);
-      launch_traverse(E, F, dir, P.tier0, P.hl, out, c->tune.trav_block, c->s);
-    }
-    {
-      Scope t(c, 3);
-      launch_narrow(E, F, dir, P.tier0, P.hl, out, c->s);
-      launch_exact(E, F, dir, P.hl, out, c->s);
-    }
+    detect_launch(c, P, dir);
     readback(c);
-    if (c->hctr->overflow & 1) throw StatusError{HFCR_E_DEVICE, "BVH traversal stack overflow"};
-    const PassCount &hp = c->hctr->pass[dir];
-    const int64_t nh = hp.hits, na = hp.amb, nc = hp.cand_n;
-    if (nc <= P.cand_cap[dir] && nh <= P.hit_cap[dir] && na <= P.amb_cap[dir]) {
-      P.cand += (int64_t)hp.cand;
-      P.f32_unsure += (int64_t)hp.f32_unsure;
-      P.exact += (int64_t)hp.exact;
-      P.visits += (int64_t)hp.visits;
+    if (detect_accept(c, P, dir)) {
       Scope t(c, 4);
-      if (sorted) sort_inplace(c, out.keys, out.vals, nh, 1 + P.hl.bits_e + P.hl.bits_f);
-      P.hits_n[dir] = nh;
-      return nh;
+      if (sorted) sort_inplace(c, ptr<uint64_t>(c->hk[dir]), ptr<uint32_t>(c->hv[dir]), P.hits_n[dir],
+                               1 + P.hl.bits_e + P.hl.bits_f);
+      return P.hits_n[dir];
     }
-    // capacity exceeded: grow and redo this pass
-    P.hit_cap[dir] = std::max<int64_t>(P.hit_cap[dir], nh + nh / 2 + 64);
-    P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], na + na / 2 + 64);
-    P.cand_cap[dir] = std::max<int64_t>(P.cand_cap[dir], nc + nc / 8 + 64);
   }
   throw StatusError{HFCR_E_DEVICE, "hit buffer did not converge"};
+}
+
+// Room for the one-launch stencil and zone stage of up to kRoundSmallHits hits.
+void ensure_round_small(hfcr_ctx *c, const Pair &P) {
+  ensure(c->parent, (size_t)std::max(P.m[0].nv + P.m[1].nv, 1) * sizeof(int));
+  ensure(c->st_keys, kRoundSmallHits * sizeof(uint64_t));
+  ensure(c->con, kRoundSmallHits * sizeof(Constraint));
+  ensure(c->zkeys, kRoundSmallHits * sizeof(uint64_t));
+  ensure(c->zvals, kRoundSmallHits * sizeof(uint32_t));
+  ensure(c->starts, (kRoundSmallHits + 1) * sizeof(uint32_t));
+}
+
+void launch_round_small(hfcr_ctx *c, Pair &P, const int *dirs, int nd, double d) {
+  Counters *dc = ptr<Counters>(c->ctr);
+  const int d0 = dirs[0], d1 = nd > 1 ? dirs[1] : dirs[0];
+  Scope t(c, 5);
+  launch_round_small(ptr<uint64_t>(c->hk[d0]), ptr<uint32_t>(c->hv[d0]), &dc->pass[d0].hits, P.hit_cap[d0],
+                     ptr<uint64_t>(c->hk[d1]), ptr<uint32_t>(c->hv[d1]), nd > 1 ? &dc->pass[d1].hits : nullptr,
+                     P.hit_cap[d1], P.hl, P.sl, P.m[0], P.m[1], d, ptr<uint64_t>(c->st_keys), ptr<Constraint>(c->con),
+                     ptr<int>(c->parent), ptr<uint64_t>(c->zkeys), ptr<uint32_t>(c->zvals), ptr<uint32_t>(c->starts),
+                     &dc->nzones, &dc->maxk, &dc->total, c->s);
+}
+
+// Detection passes of the directions dirs[0..nd) followed at once by the
+// one-launch stencil and zone stage on their hits, with a single readback.
+// Every pass that overflowed its buffers is redone.  Returns whether the
+// stage's results stand (every pass fit the first time; the stage itself ran
+// only for 1..kRoundSmallHits hits).
+bool detect_and_round_small(hfcr_ctx *c, Pair &P, const int *dirs, int nd, double d) {
+  for (int q = 0; q < nd; ++q) detect_launch(c, P, dirs[q]);
+  ensure_round_small(c, P);
+  launch_round_small(c, P, dirs, nd, d);
+  readback(c);
+  bool fit[2] = {true, true};
+  for (int q = 0; q < nd; ++q) fit[q] = detect_accept(c, P, dirs[q]);
+  bool ok = true;
+  for (int q = 0; q < nd; ++q)
+    if (!fit[q]) {
+      detect_dir(c, P, dirs[q], false);
+      ok = false;
+    }
+  return ok;
 }
 
 // Unique stencil keys of the hits of the listed directions into c->st_keys.
@@ -447,21 +505,34 @@ struct RoundInfo {
   int maxk = 0;
 };
 
-// Constraints, impact zones, solve and update for the stencils in c->st_keys.
-RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
+// Stencils, constraints, impact zones, solve and update of one round for the
+// hits of the active directions act[0..nact).  `staged`: the one-launch
+// stencil and zone stage already ran on these hits and its counts are in the
+// last readback.
+RoundInfo respond(hfcr_ctx *c, Pair &P, const int *act, int nact, double d, hfcr_stats *st, bool staged) {
   RoundInfo info;
-  info.S = S;
   Counters *dc = ptr<Counters>(c->ctr);
   const int nvt = P.m[0].nv + P.m[1].nv;
-  const int bits_s = bits_for(S);
-  {
-    Scope t(c, 4);
-    ensure(c->con, S * sizeof(Constraint));
-    launch_constraints(ptr<uint64_t>(c->st_keys), S, P.sl, P.m[0], P.m[1], d, ptr<Constraint>(c->con), c->s);
+  const int64_t nh = P.hits_n[act[0]] + (nact > 1 ? P.hits_n[act[1]] : 0);
+  bool fused = staged;
+  if (!staged && nh <= kRoundSmallHits) {
+    // stencils, constraints and zones in one launch, and one readback for
+    // their counts
+    ensure_round_small(c, P);
+    launch_round_small(c, P, act, nact, d);
+    fused = true;
   }
-  {
-    Scope t(c, 5);
+  int64_t S = 0;
+  if (!fused) {
     ensure(c->parent, (size_t)std::max(nvt, 1) * sizeof(int));
+    S = build_stencils(c, P, act, nact, c->st_keys);
+    const int bits_s = bits_for(S);
+    {
+      Scope t(c, 4);
+      ensure(c->con, S * sizeof(Constraint));
+      launch_constraints(ptr<uint64_t>(c->st_keys), S, P.sl, P.m[0], P.m[1], d, ptr<Constraint>(c->con), c->s);
+    }
+    Scope t(c, 5);
     ensure(c->zkeys, S * sizeof(uint64_t));
     ensure(c->zvals, S * sizeof(uint32_t));
     ensure(c->starts, (S + 1) * sizeof(uint32_t));
@@ -481,7 +552,10 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, int64_t S, double d, hfcr_stats *st) {
                          &dc->nzones, &dc->maxk, c->s);
     }
   }
-  readback(c);
+  if (!staged) readback(c);
+  if (fused) S = c->hctr->total;
+  info.S = S;
+  const int bits_s = bits_for(S);
   info.nzones = (int)c->hctr->nzones;
   info.maxk = (int)c->hctr->maxk;
   if (info.maxk > HFCR_MAX_ZONE)
@@ -825,8 +899,20 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
         int64_t nhits = 0, nf = 0, ns = 0;
         bool second_done = false;
         const int first = (int)(((int64_t)r + o.round_offset) & 1);
+        // rounds after the first (and before the last) start the stencil and
+        // zone stage right behind detection; it stands when the round's hits
+        // fit it
+        const bool speculate = r > 0 && r < o.max_rounds;
+        bool fit = false, staged = false;
+        if (speculate) {
+          int sd[2], nsd = 0;
+          if (alternate) sd[nsd++] = first;
+          else
+            for (int q = 0; q < P.ndirs; ++q) sd[nsd++] = P.dirs[q];
+          fit = detect_and_round_small(c, P, sd, nsd, d);
+        }
         if (alternate) {
-          nf = detect_dir(c, P, first, r == 0);
+          nf = speculate ? P.hits_n[first] : detect_dir(c, P, first, r == 0);
           second_done = r == 0 || nf == 0;
           if (second_done) ns = detect_dir(c, P, 1 - first, r == 0);
           else P.hits_n[1 - first] = 0;
@@ -841,7 +927,7 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
         } else {
           for (int q = 0; q < P.ndirs; ++q) {
             const int dir = P.dirs[q];
-            const int64_t n = detect_dir(c, P, dir, r == 0);
+            const int64_t n = speculate ? P.hits_n[dir] : detect_dir(c, P, dir, r == 0);
             if (n > 0) {
               act[nact++] = dir;
               nhits += n;
@@ -849,6 +935,9 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
           }
           if (r == 0) write_hit_outputs(c, P, res, st, truncated);
         }
+        // the staged results belong to the active hits only if no other
+        // detection or readback came between
+        staged = fit && nhits > 0 && nhits <= kRoundSmallHits && (!alternate || nf > 0);
         if (st && r < HFCR_STAT_ROUNDS) st->round_hits[r] = (int32_t)nhits;
         if (nact == 0) {
           converged = true;
@@ -860,10 +949,9 @@ hfcr_status hfcr_resolve(hfcr_ctx *c, const hfcr_mesh *a, const hfcr_mesh *b, in
           if (alternate) residual = nf + (second_done ? ns : detect_dir(c, P, 1 - first, false));
           break;
         }
-        const int64_t S = build_stencils(c, P, act, nact, c->st_keys);
-        RoundInfo info = respond(c, P, S, d, st);
+        RoundInfo info = respond(c, P, act, nact, d, st, staged);
         if (st && r < HFCR_STAT_ROUNDS) {
-          st->round_stencils[r] = (int32_t)S;
+          st->round_stencils[r] = (int32_t)info.S;
           st->round_zones[r] = info.nzones;
           st->round_max_zone[r] = info.maxk;
         }

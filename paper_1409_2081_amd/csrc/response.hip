@@ -61,17 +61,14 @@ void launch_compact_keys(const uint64_t *keys, const uint32_t *flags, const uint
   if (n > 0) k_compact_keys<<<grid_for(n, 256), 256, 0, s>>>(keys, flags, pos, n, out);
 }
 
-// The stencil build (keys of up to two hit lists, sort, unique, compaction)
-// for at most 1024 hits in one workgroup; the same keys, order and count as
-// the multi-kernel path.
-__global__ __launch_bounds__(1024) void k_stencils_small(const uint64_t *__restrict__ hk0,
-                                                         const uint32_t *__restrict__ hv0, int n0,
-                                                         const uint64_t *__restrict__ hk1,
-                                                         const uint32_t *__restrict__ hv1, int n1, HitLayout hl,
-                                                         StencilLayout sl, uint64_t *out, uint32_t *total) {
-  __shared__ uint64_t sk[1024];
-  __shared__ uint32_t sv[1024];
-  __shared__ uint32_t wsum[1024 / kWave];
+// The stencil build for at most 1024 hits in one workgroup (keys of up to two
+// hit lists, sorting network, unique, compaction): the same keys, order and
+// count as the multi-kernel path.  The unique keys go to out[0..count) and to
+// sk[0..count); every thread gets the count.
+__device__ uint32_t stencils_wg(const uint64_t *__restrict__ hk0, const uint32_t *__restrict__ hv0, int n0,
+                                const uint64_t *__restrict__ hk1, const uint32_t *__restrict__ hv1, int n1,
+                                HitLayout hl, StencilLayout sl, uint64_t *out, uint64_t *sk, uint32_t *sv,
+                                uint32_t *wsum) {
   const int t = threadIdx.x;
   const int n = n0 + n1;
   uint64_t k = ~0ull;
@@ -98,8 +95,24 @@ __global__ __launch_bounds__(1024) void k_stencils_small(const uint64_t *__restr
     if (w < wave) before += wsum[w];
     count += wsum[w];
   }
-  if (flag) out[before + (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = k;
-  if (t == 0) *total = count;
+  const uint32_t pos = before + (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull));
+  if (flag) out[pos] = k;
+  __syncthreads();  // every read of sk and wsum above is done
+  if (flag) sk[pos] = k;
+  __syncthreads();
+  return count;
+}
+
+__global__ __launch_bounds__(1024) void k_stencils_small(const uint64_t *__restrict__ hk0,
+                                                         const uint32_t *__restrict__ hv0, int n0,
+                                                         const uint64_t *__restrict__ hk1,
+                                                         const uint32_t *__restrict__ hv1, int n1, HitLayout hl,
+                                                         StencilLayout sl, uint64_t *out, uint32_t *total) {
+  __shared__ uint64_t sk[1024];
+  __shared__ uint32_t sv[1024];
+  __shared__ uint32_t wsum[1024 / kWave];
+  const uint32_t count = stencils_wg(hk0, hv0, n0, hk1, hv1, n1, hl, sl, out, sk, sv, wsum);
+  if (threadIdx.x == 0) *total = count;
 }
 
 bool launch_stencils_small(const uint64_t *hk0, const uint32_t *hv0, int64_t n0, const uint64_t *hk1,
@@ -130,11 +143,9 @@ struct MeshView {
   int nv;
 };
 
-__global__ void k_constraints(const uint64_t *__restrict__ keys, int64_t S, StencilLayout sl, MeshView A,
-                              MeshView B, double d, Constraint *con) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S) return;
-  uint64_t k = keys[i];
+// Constraint of the stencil with key k (Eq. 1, Eq. 2, Eq. 8).
+__device__ Constraint make_constraint(uint64_t k, StencilLayout sl, const MeshView &A, const MeshView &B,
+                                      double d) {
   int dir = (int)(k >> (sl.bits_v + sl.bits_f));
   int x0 = (int)((k >> sl.bits_f) & ((1ull << sl.bits_v) - 1));
   int f = (int)(k & ((1ull << sl.bits_f) - 1));
@@ -168,7 +179,14 @@ __global__ void k_constraints(const uint64_t *__restrict__ keys, int64_t S, Sten
   const int off_e = dir == 0 ? 0 : A.nv;  // global id offset of the edge mesh
   const int off_f = dir == 0 ? A.nv : 0;  // and of the face mesh
   out.v = make_int4(off_e + x0, off_f + t0, off_f + t1, off_f + t2);
-  con[i] = out;
+  return out;
+}
+
+__global__ void k_constraints(const uint64_t *__restrict__ keys, int64_t S, StencilLayout sl, MeshView A,
+                              MeshView B, double d, Constraint *con) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  con[i] = make_constraint(keys[i], sl, A, B, d);
 }
 
 void launch_constraints(const uint64_t *keys, int64_t S, StencilLayout sl, const MeshDev &A, const MeshDev &B,
@@ -289,17 +307,13 @@ void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, u
 // path, so every output is identical.  clear[0] receives the largest zone,
 // clear[1] (the solve's retry counter) is zeroed.
 constexpr int kZonesSmall = 1024;
+static_assert(kRoundSmallHits <= kZonesSmall, "the fused round uses the one-workgroup zone stage");
 
-__global__ __launch_bounds__(1024) void k_zones_small(const Constraint *__restrict__ con, int S, int *parent,
-                                                      int bits_s, uint64_t *keys, uint32_t *vals,
-                                                      uint32_t *starts, uint32_t *nz, uint32_t *clear) {
-  __shared__ uint64_t sk[1024];
-  __shared__ uint32_t sv[1024];
-  __shared__ uint32_t wsum[1024 / kWave];
-  __shared__ uint32_t sst[1024 + 1];
+// Thread t holds stencil t's vertices v (act = t < S).
+__device__ void zones_wg(int4 v, bool act, int S, int *parent, int bits_s, uint64_t *keys, uint32_t *vals,
+                         uint32_t *starts, uint32_t *nz, uint32_t *clear, uint64_t *sk, uint32_t *sv,
+                         uint32_t *wsum, uint32_t *sst) {
   const int t = threadIdx.x;
-  const bool act = t < S;
-  const int4 v = act ? con[t].v : make_int4(0, 0, 0, 0);
   if (act) {
     parent[v.x] = v.x;
     parent[v.y] = v.y;
@@ -364,11 +378,75 @@ __global__ __launch_bounds__(1024) void k_zones_small(const Constraint *__restri
   }
 }
 
+__global__ __launch_bounds__(1024) void k_zones_small(const Constraint *__restrict__ con, int S, int *parent,
+                                                      int bits_s, uint64_t *keys, uint32_t *vals,
+                                                      uint32_t *starts, uint32_t *nz, uint32_t *clear) {
+  __shared__ uint64_t sk[1024];
+  __shared__ uint32_t sv[1024];
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t sst[1024 + 1];
+  const int t = threadIdx.x;
+  const bool act = t < S;
+  const int4 v = act ? con[t].v : make_int4(0, 0, 0, 0);
+  zones_wg(v, act, S, parent, bits_s, keys, vals, starts, nz, clear, sk, sv, wsum, sst);
+}
+
 bool launch_zones_small(const Constraint *con, int64_t S, int *parent, int bits_s, uint64_t *keys, uint32_t *vals,
                         uint32_t *starts, uint32_t *nz, uint32_t *clear, hipStream_t s) {
   if (S <= 0 || S > kZonesSmall) return false;
   k_zones_small<<<1, 1024, 0, s>>>(con, (int)S, parent, bits_s, keys, vals, starts, nz, clear);
   return true;
+}
+
+// Stencils, constraints and impact zones of one round for at most kZonesSmall
+// hits in one workgroup: the three stages above in sequence, with the same
+// outputs (stencil keys, constraints, zone keys, order, starts, counts); the
+// stencil count goes to *total.  The hit counts are read from the detection
+// pass's own counters (cnt1 null: no second list), so the launch can follow
+// the pass before the host has seen them; a list that overflowed its buffer
+// (count > cap), more than kZonesSmall hits or none leave *total = 0 and
+// nothing else written.
+__global__ __launch_bounds__(1024) void k_round_small(const uint64_t *__restrict__ hk0,
+                                                      const uint32_t *__restrict__ hv0, const uint32_t *cnt0,
+                                                      int64_t cap0, const uint64_t *__restrict__ hk1,
+                                                      const uint32_t *__restrict__ hv1, const uint32_t *cnt1,
+                                                      int64_t cap1, HitLayout hl, StencilLayout sl, MeshView A,
+                                                      MeshView B, double d, uint64_t *st_keys, Constraint *con,
+                                                      int *parent, uint64_t *keys, uint32_t *vals, uint32_t *starts,
+                                                      uint32_t *nz, uint32_t *clear, uint32_t *total) {
+  __shared__ uint64_t sk[1024];
+  __shared__ uint32_t sv[1024];
+  __shared__ uint32_t wsum[1024 / kWave];
+  __shared__ uint32_t sst[1024 + 1];
+  const int t = threadIdx.x;
+  const int64_t n0 = *cnt0, n1 = cnt1 ? *cnt1 : 0;
+  if (n0 > cap0 || n1 > cap1 || n0 + n1 <= 0 || n0 + n1 > kRoundSmallHits) {
+    if (t == 0) *total = 0u;
+    return;
+  }
+  const int S = (int)stencils_wg(hk0, hv0, (int)n0, hk1, hv1, (int)n1, hl, sl, st_keys, sk, sv, wsum);
+  const bool act = t < S;
+  int4 v = make_int4(0, 0, 0, 0);
+  if (act) {
+    const Constraint cn = make_constraint(sk[t], sl, A, B, d);
+    con[t] = cn;
+    v = cn.v;
+  }
+  // zones_wg passes two barriers before its sorting network reuses sk
+  int bits_s = 1;
+  while (bits_s < 62 && (1 << bits_s) < S) ++bits_s;
+  zones_wg(v, act, S, parent, bits_s, keys, vals, starts, nz, clear, sk, sv, wsum, sst);
+  if (t == 0) *total = (uint32_t)S;
+}
+
+void launch_round_small(const uint64_t *hk0, const uint32_t *hv0, const uint32_t *cnt0, int64_t cap0,
+                        const uint64_t *hk1, const uint32_t *hv1, const uint32_t *cnt1, int64_t cap1, HitLayout hl,
+                        StencilLayout sl, const MeshDev &A, const MeshDev &B, double d, uint64_t *st_keys,
+                        Constraint *con, int *parent, uint64_t *keys, uint32_t *vals, uint32_t *starts, uint32_t *nz,
+                        uint32_t *clear, uint32_t *total, hipStream_t s) {
+  MeshView a{A.x64, A.tri_in, A.nv}, b{B.x64, B.tri_in, B.nv};
+  k_round_small<<<1, 1024, 0, s>>>(hk0, hv0, cnt0, cap0, hk1, hv1, cnt1, cap1, hl, sl, a, b, d, st_keys, con, parent,
+                                   keys, vals, starts, nz, clear, total);
 }
 
 // -------------------------------------------------------------- zone solve
