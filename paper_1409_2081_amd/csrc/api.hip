@@ -424,7 +424,6 @@ int64_t detect_dir(hfcr_ctx *c, Pair &P, int dir, bool sorted = true) {
 
 // Room for the one-launch stencil and zone stage of up to kRoundSmallHits hits.
 void ensure_round_small(hfcr_ctx *c, const Pair &P) {
-  ensure(c->parent, (size_t)std::max(P.m[0].nv + P.m[1].nv, 1) * sizeof(int));
   ensure(c->st_keys, kRoundSmallHits * sizeof(uint64_t));
   ensure(c->con, kRoundSmallHits * sizeof(Constraint));
   ensure(c->zkeys, kRoundSmallHits * sizeof(uint64_t));
@@ -439,8 +438,8 @@ void launch_round_small(hfcr_ctx *c, Pair &P, const int *dirs, int nd, double d)
   launch_round_small(ptr<uint64_t>(c->hk[d0]), ptr<uint32_t>(c->hv[d0]), &dc->pass[d0].hits, P.hit_cap[d0],
                      ptr<uint64_t>(c->hk[d1]), ptr<uint32_t>(c->hv[d1]), nd > 1 ? &dc->pass[d1].hits : nullptr,
                      P.hit_cap[d1], P.hl, P.sl, P.m[0], P.m[1], d, ptr<uint64_t>(c->st_keys), ptr<Constraint>(c->con),
-                     ptr<int>(c->parent), ptr<uint64_t>(c->zkeys), ptr<uint32_t>(c->zvals), ptr<uint32_t>(c->starts),
-                     &dc->nzones, &dc->maxk, &dc->total, c->s);
+                     ptr<uint64_t>(c->zkeys), ptr<uint32_t>(c->zvals), ptr<uint32_t>(c->starts), &dc->nzones,
+                     &dc->maxk, &dc->total, c->s);
 }
 
 // Detection passes of the directions dirs[0..nd) followed at once by the
@@ -536,8 +535,8 @@ RoundInfo respond(hfcr_ctx *c, Pair &P, const int *act, int nact, double d, hfcr
     ensure(c->zkeys, S * sizeof(uint64_t));
     ensure(c->zvals, S * sizeof(uint32_t));
     ensure(c->starts, (S + 1) * sizeof(uint32_t));
-    if (!launch_zones_small(ptr<Constraint>(c->con), S, ptr<int>(c->parent), bits_s, ptr<uint64_t>(c->zkeys),
-                            ptr<uint32_t>(c->zvals), ptr<uint32_t>(c->starts), &dc->nzones, &dc->maxk, c->s)) {
+    if (!launch_zones_small(ptr<Constraint>(c->con), S, bits_s, ptr<uint64_t>(c->zkeys), ptr<uint32_t>(c->zvals),
+                            ptr<uint32_t>(c->starts), &dc->nzones, &dc->maxk, c->s)) {
       launch_uf_init(ptr<int>(c->parent), nvt, &dc->maxk, c->s);
       launch_uf_union(ptr<Constraint>(c->con), S, ptr<int>(c->parent), c->s);
       launch_zone_keys(ptr<Constraint>(c->con), S, ptr<int>(c->parent), bits_s, ptr<uint64_t>(c->zkeys),

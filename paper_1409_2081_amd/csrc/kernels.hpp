@@ -92,7 +92,7 @@ void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, u
                         uint32_t *nzones_out, uint32_t *maxk_out, hipStream_t s);
 // The zone stage (uf_init .. zone_starts) in one launch when S is small
 // enough; returns false (and launches nothing) otherwise.
-bool launch_zones_small(const Constraint *con, int64_t S, int *parent, int bits_s, uint64_t *keys, uint32_t *vals,
+bool launch_zones_small(const Constraint *con, int64_t S, int bits_s, uint64_t *keys, uint32_t *vals,
                         uint32_t *starts, uint32_t *nzones_out, uint32_t *clear, hipStream_t s);
 
 // Stencils, constraints and the zone stage of one round (the three launches
@@ -106,8 +106,8 @@ constexpr int kRoundSmallHits = 1024;
 void launch_round_small(const uint64_t *hk0, const uint32_t *hv0, const uint32_t *cnt0, int64_t cap0,
                         const uint64_t *hk1, const uint32_t *hv1, const uint32_t *cnt1, int64_t cap1, HitLayout hl,
                         StencilLayout sl, const MeshDev &A, const MeshDev &B, double d, uint64_t *st_keys,
-                        Constraint *con, int *parent, uint64_t *keys, uint32_t *vals, uint32_t *starts,
-                        uint32_t *nzones_out, uint32_t *clear, uint32_t *total, hipStream_t s);
+                        Constraint *con, uint64_t *keys, uint32_t *vals, uint32_t *starts, uint32_t *nzones_out,
+                        uint32_t *clear, uint32_t *total, hipStream_t s);
 
 struct SolveArgs {
   const Constraint *con;

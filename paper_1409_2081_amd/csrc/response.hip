@@ -301,36 +301,83 @@ void launch_zone_starts(const uint32_t *flags, const uint32_t *pos, int64_t S, u
   k_zone_maxk<<<64, 256, 0, s>>>(starts, nz, maxk);
 }
 
-// The whole zone stage for at most kZonesSmall stencils in one workgroup:
-// the same union-find (only the stencils' vertices are reset), keys (root,
-// stencil), sorting network, segment flags and starts as the multi-kernel
-// path, so every output is identical.  clear[0] receives the largest zone,
-// clear[1] (the solve's retry counter) is zeroed.
+// The whole zone stage for at most kZonesSmall stencils in one workgroup: the
+// same components, keys (root, stencil), sorting network, segment flags and
+// starts as the multi-kernel path, so every output is identical.  The
+// union-find runs in LDS on a hash table of the stencils' vertex ids (slot =
+// open addressing on the id), hooking the root with the larger vertex id under
+// the other, so every root is again its component's smallest id.  clear[0]
+// receives the largest zone, clear[1] (the solve's retry counter) is zeroed.
 constexpr int kZonesSmall = 1024;
+constexpr int kUfSlots = 8192;  // at least twice the 4 * kZonesSmall vertex ids
 static_assert(kRoundSmallHits <= kZonesSmall, "the fused round uses the one-workgroup zone stage");
+static_assert(kUfSlots >= 8 * kZonesSmall && (kUfSlots & (kUfSlots - 1)) == 0, "hash table size");
 
-// Thread t holds stencil t's vertices v (act = t < S).
-__device__ void zones_wg(int4 v, bool act, int S, int *parent, int bits_s, uint64_t *keys, uint32_t *vals,
-                         uint32_t *starts, uint32_t *nz, uint32_t *clear, uint64_t *sk, uint32_t *sv,
-                         uint32_t *wsum, uint32_t *sst) {
+// Slot of vertex id v in the table (inserted if absent).  Terminates: the
+// table holds at most half as many ids as slots.
+__device__ inline int uf_slot(int *key, int v) {
+  uint32_t h = ((uint32_t)v * 2654435761u) >> 19;  // the top 13 bits: 0 .. kUfSlots - 1
+  while (true) {
+    const int old = atomicCAS(key + h, -1, v);
+    if (old == -1 || old == v) return (int)h;
+    h = (h + 1) & (kUfSlots - 1);
+  }
+}
+
+__device__ inline int lds_uf_find(int *par, int x) {
+  while (true) {
+    const int p = __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (p == x) return x;
+    const int gp = __hip_atomic_load(par + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (gp != p) __hip_atomic_store(par + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // path halving
+    x = gp;
+  }
+}
+
+__device__ inline void lds_uf_unite(int *par, const int *key, int a, int b) {
+  while (true) {
+    a = lds_uf_find(par, a);
+    b = lds_uf_find(par, b);
+    if (a == b) return;
+    if (key[a] < key[b]) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    // hook root a (the larger vertex id) under root b
+    if (atomicCAS(par + a, a, b) == a) return;
+  }
+}
+
+// Thread t holds stencil t's vertices v (act = t < S); hkey and hpar are the
+// LDS hash table (kUfSlots entries each).
+__device__ void zones_wg(int4 v, bool act, int S, int bits_s, uint64_t *keys, uint32_t *vals, uint32_t *starts,
+                         uint32_t *nz, uint32_t *clear, uint64_t *sk, uint32_t *sv, uint32_t *wsum, uint32_t *sst,
+                         int *hkey, int *hpar) {
   const int t = threadIdx.x;
+  for (int i = t; i < kUfSlots; i += blockDim.x) {
+    hkey[i] = -1;
+    hpar[i] = i;
+  }
+  __syncthreads();
+  int s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   if (act) {
-    parent[v.x] = v.x;
-    parent[v.y] = v.y;
-    parent[v.z] = v.z;
-    parent[v.w] = v.w;
+    s0 = uf_slot(hkey, v.x);
+    s1 = uf_slot(hkey, v.y);
+    s2 = uf_slot(hkey, v.z);
+    s3 = uf_slot(hkey, v.w);
   }
   __syncthreads();
   if (act) {
-    uf_unite(parent, v.x, v.y);
-    uf_unite(parent, v.x, v.z);
-    uf_unite(parent, v.x, v.w);
+    lds_uf_unite(hpar, hkey, s0, s1);
+    lds_uf_unite(hpar, hkey, s0, s2);
+    lds_uf_unite(hpar, hkey, s0, s3);
   }
   __syncthreads();
   uint64_t k = ~0ull;
   uint32_t val = 0;
   if (act) {
-    k = ((uint64_t)uf_find(parent, v.x) << bits_s) | (uint64_t)t;
+    k = ((uint64_t)hkey[lds_uf_find(hpar, s0)] << bits_s) | (uint64_t)t;
     val = (uint32_t)t;
   }
   int P = 2;
@@ -378,23 +425,25 @@ __device__ void zones_wg(int4 v, bool act, int S, int *parent, int bits_s, uint6
   }
 }
 
-__global__ __launch_bounds__(1024) void k_zones_small(const Constraint *__restrict__ con, int S, int *parent,
-                                                      int bits_s, uint64_t *keys, uint32_t *vals,
-                                                      uint32_t *starts, uint32_t *nz, uint32_t *clear) {
+__global__ __launch_bounds__(1024) void k_zones_small(const Constraint *__restrict__ con, int S, int bits_s,
+                                                      uint64_t *keys, uint32_t *vals, uint32_t *starts,
+                                                      uint32_t *nz, uint32_t *clear) {
   __shared__ uint64_t sk[1024];
   __shared__ uint32_t sv[1024];
   __shared__ uint32_t wsum[1024 / kWave];
   __shared__ uint32_t sst[1024 + 1];
+  __shared__ int hkey[kUfSlots];
+  __shared__ int hpar[kUfSlots];
   const int t = threadIdx.x;
   const bool act = t < S;
   const int4 v = act ? con[t].v : make_int4(0, 0, 0, 0);
-  zones_wg(v, act, S, parent, bits_s, keys, vals, starts, nz, clear, sk, sv, wsum, sst);
+  zones_wg(v, act, S, bits_s, keys, vals, starts, nz, clear, sk, sv, wsum, sst, hkey, hpar);
 }
 
-bool launch_zones_small(const Constraint *con, int64_t S, int *parent, int bits_s, uint64_t *keys, uint32_t *vals,
+bool launch_zones_small(const Constraint *con, int64_t S, int bits_s, uint64_t *keys, uint32_t *vals,
                         uint32_t *starts, uint32_t *nz, uint32_t *clear, hipStream_t s) {
   if (S <= 0 || S > kZonesSmall) return false;
-  k_zones_small<<<1, 1024, 0, s>>>(con, (int)S, parent, bits_s, keys, vals, starts, nz, clear);
+  k_zones_small<<<1, 1024, 0, s>>>(con, (int)S, bits_s, keys, vals, starts, nz, clear);
   return true;
 }
 
@@ -412,12 +461,14 @@ __global__ __launch_bounds__(1024) void k_round_small(const uint64_t *__restrict
                                                       const uint32_t *__restrict__ hv1, const uint32_t *cnt1,
                                                       int64_t cap1, HitLayout hl, StencilLayout sl, MeshView A,
                                                       MeshView B, double d, uint64_t *st_keys, Constraint *con,
-                                                      int *parent, uint64_t *keys, uint32_t *vals, uint32_t *starts,
-                                                      uint32_t *nz, uint32_t *clear, uint32_t *total) {
+                                                      uint64_t *keys, uint32_t *vals, uint32_t *starts, uint32_t *nz,
+                                                      uint32_t *clear, uint32_t *total) {
   __shared__ uint64_t sk[1024];
   __shared__ uint32_t sv[1024];
   __shared__ uint32_t wsum[1024 / kWave];
   __shared__ uint32_t sst[1024 + 1];
+  __shared__ int hkey[kUfSlots];
+  __shared__ int hpar[kUfSlots];
   const int t = threadIdx.x;
   const int64_t n0 = *cnt0, n1 = cnt1 ? *cnt1 : 0;
   if (n0 > cap0 || n1 > cap1 || n0 + n1 <= 0 || n0 + n1 > kRoundSmallHits) {
@@ -432,21 +483,21 @@ __global__ __launch_bounds__(1024) void k_round_small(const uint64_t *__restrict
     con[t] = cn;
     v = cn.v;
   }
-  // zones_wg passes two barriers before its sorting network reuses sk
+  // zones_wg passes three barriers before its sorting network reuses sk
   int bits_s = 1;
   while (bits_s < 62 && (1 << bits_s) < S) ++bits_s;
-  zones_wg(v, act, S, parent, bits_s, keys, vals, starts, nz, clear, sk, sv, wsum, sst);
+  zones_wg(v, act, S, bits_s, keys, vals, starts, nz, clear, sk, sv, wsum, sst, hkey, hpar);
   if (t == 0) *total = (uint32_t)S;
 }
 
 void launch_round_small(const uint64_t *hk0, const uint32_t *hv0, const uint32_t *cnt0, int64_t cap0,
                         const uint64_t *hk1, const uint32_t *hv1, const uint32_t *cnt1, int64_t cap1, HitLayout hl,
                         StencilLayout sl, const MeshDev &A, const MeshDev &B, double d, uint64_t *st_keys,
-                        Constraint *con, int *parent, uint64_t *keys, uint32_t *vals, uint32_t *starts, uint32_t *nz,
+                        Constraint *con, uint64_t *keys, uint32_t *vals, uint32_t *starts, uint32_t *nz,
                         uint32_t *clear, uint32_t *total, hipStream_t s) {
   MeshView a{A.x64, A.tri_in, A.nv}, b{B.x64, B.tri_in, B.nv};
-  k_round_small<<<1, 1024, 0, s>>>(hk0, hv0, cnt0, cap0, hk1, hv1, cnt1, cap1, hl, sl, a, b, d, st_keys, con, parent,
-                                   keys, vals, starts, nz, clear, total);
+  k_round_small<<<1, 1024, 0, s>>>(hk0, hv0, cnt0, cap0, hk1, hv1, cnt1, cap1, hl, sl, a, b, d, st_keys, con, keys,
+                                   vals, starts, nz, clear, total);
 }
 
 // -------------------------------------------------------------- zone solve
