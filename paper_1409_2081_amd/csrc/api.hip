@@ -331,7 +331,10 @@ void build_bvh(hfcr_ctx *c, Pair &P, int i) {
   P.dirty[i] = true;
 }
 
-void reset_counters(hfcr_ctx *c) { HIP_CHECK(hipMemsetAsync(c->ctr.p, 0, sizeof(Counters), c->s)); }
+static_assert(sizeof(Counters) % 4 == 0 && sizeof(PassCount) % 4 == 0, "counters are zeroed as 32-bit words");
+void reset_counters(hfcr_ctx *c) {
+  launch_zero_words(ptr<uint32_t>(c->ctr), (int)(sizeof(Counters) / 4), c->s);
+}
 
 // Launches one detection pass in direction dir (refitting the face side's
 // tree first if its positions changed); the counts are read back later.
@@ -354,7 +357,7 @@ void detect_launch(hfcr_ctx *c, Pair &P, int dir) {
   P.amb_cap[dir] = std::max<int64_t>(P.amb_cap[dir], (int64_t)(c->amb[dir].bytes / sizeof(uint2)));
   P.cand_cap[dir] = std::max<int64_t>(P.cand_cap[dir], (int64_t)(c->cand.bytes / sizeof(uint2)));
   PassCount *pc = &dc->pass[dir];
-  HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(PassCount), c->s));
+  launch_zero_words(reinterpret_cast<uint32_t *>(pc), (int)(sizeof(PassCount) / 4), c->s);
   DcdOut out;
   out.keys = ptr<uint64_t>(c->hk[dir]);
   out.vals = ptr<uint32_t>(c->hv[dir]);

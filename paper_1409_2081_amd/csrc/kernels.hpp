@@ -77,6 +77,8 @@ void launch_constraints(const uint64_t *st_keys, int64_t S, StencilLayout sl, co
                         double d, Constraint *con, hipStream_t s);
 // Also sets *clear to 0 (may be null).
 // parent[i] = i; also zeroes clear[0] and clear[1] (when clear is not null)
+// p[0..n) = 0 (n 32-bit words), one launch.
+void launch_zero_words(uint32_t *p, int n, hipStream_t s);
 void launch_uf_init(int *parent, int n, uint32_t *clear, hipStream_t s);
 void launch_uf_union(const Constraint *con, int64_t S, int *parent, hipStream_t s);
 // Stencil keys of up to two hit lists, sorted and made unique, written to

@@ -305,4 +305,14 @@ void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *block_sums
   if (total_dev) k_copy_total<<<1, 1, 0, s>>>(block_sums, nb, in, out, n, total_dev);
 }
 
+// Zero n 32-bit words in one launch (a runtime memset of a few dozen bytes can
+// take several fill launches when the address is not 16-byte aligned).
+__global__ void k_zero_words(uint32_t *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+void launch_zero_words(uint32_t *p, int n, hipStream_t s) {
+  if (n > 0) k_zero_words<<<1, 256, 0, s>>>(p, n);
+}
+
 }  // namespace hfcr
