@@ -1252,6 +1252,8 @@ __global__ __launch_bounds__(1024) void k_update_small(const Constraint *__restr
                                                        const double *__restrict__ lambda, MeshOut A, MeshOut B) {
   __shared__ uint64_t sk[1024];
   __shared__ uint32_t sv[1024];
+  // each stencil's lambda and normal, so the per-vertex gathers below read LDS
+  __shared__ double sl[256], snx[256], sny[256], snz[256];
   const int t = threadIdx.x;
   const int n = 4 * S;
   const int shift = bits_s + 2;
@@ -1263,9 +1265,16 @@ __global__ __launch_bounds__(1024) void k_update_small(const Constraint *__restr
     const int vert = slot == 0 ? v.x : slot == 1 ? v.y : slot == 2 ? v.z : v.w;
     k = ((uint64_t)vert << shift) | (uint64_t)t;
   }
+  if (t < S) {
+    const double4 nn = con[t].n;
+    sl[t] = lambda[t];
+    snx[t] = nn.x;
+    sny[t] = nn.y;
+    snz[t] = nn.z;
+  }
   int P = 2;
   while (P < n) P <<= 1;
-  wg_bitonic_1k(k, unused, P, sk, sv);
+  wg_bitonic_1k(k, unused, P, sk, sv);  // ends with a barrier: the stencil arrays are visible
   sk[t] = k;
   __syncthreads();
   if (t >= n) return;
@@ -1277,11 +1286,10 @@ __global__ __launch_bounds__(1024) void k_update_small(const Constraint *__restr
     const int64_t s = (int64_t)(low >> 2);
     const int slot = (int)(low & 3);
     const double c = slot == 0 ? 1.0 : -1.0 / 3.0;
-    const double4 nn = con[s].n;
-    const double g = c * lambda[s];
-    sx += g * nn.x;
-    sy += g * nn.y;
-    sz += g * nn.z;
+    const double g = c * sl[s];
+    sx += g * snx[s];
+    sy += g * sny[s];
+    sz += g * snz[s];
   }
   const bool in_a = (int64_t)vtx < A.nv;
   MeshOut &M = in_a ? A : B;
@@ -1306,7 +1314,7 @@ __global__ __launch_bounds__(1024) void k_update_small(const Constraint *__restr
 
 bool launch_update_small(const Constraint *con, int64_t S, int bits_s, const double *lambda, MeshDev &A,
                          MeshDev &B, hipStream_t s) {
-  if (S <= 0 || 4 * S > 1024) return false;
+  if (S <= 0 || 4 * S > 1024) return false;  // S <= 256: the kernel's stencil arrays
   MeshOut a{A.x64, A.f32 ? A.x32 : nullptr, A.nv, A.inv_mass};
   MeshOut b{B.x64, B.f32 ? B.x32 : nullptr, B.nv, B.inv_mass};
   k_update_small<<<1, 1024, 0, s>>>(con, (int)S, bits_s, lambda, a, b);
