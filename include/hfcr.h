@@ -127,7 +127,10 @@ typedef struct {
 #define HFCR_STAT_ROUNDS 64
 #define HFCR_STAGES 8 /* stage_ms: 0 setup+topology, 1 refit, 2 traverse,
                          3 narrow phase (filters and exact tier),
-                         4 stencils, 5 zones, 6 solve, 7 update             */
+                         4 stencils and constraints (and the round-0 hit
+                         sort), 5 zones (a round with at most 1024 active
+                         hits builds its stencils, constraints and zones in
+                         one launch, timed here), 6 solve, 7 update       */
 
 typedef struct {
   int32_t rounds;            /* responses performed                          */
