@@ -572,6 +572,7 @@ __host__ __device__ inline size_t zone_lds_bytes(bool mat_lds, int kcap) {
 // matrix is padded to a multiple of 8 with diag = max diag A (so padded
 // rows never trip the pivot test) and rhs 0.
 constexpr int TB = 8;
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));  // an fp64 MFMA accumulator
 __device__ inline int64_t tile_off(int I, int J) { return ((int64_t)I * (I + 1) / 2 + J) * (TB * TB); }
 __device__ inline int sw(int r, int c) { return r * TB + (c ^ r); }
 
@@ -701,37 +702,49 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
       rhs[I * TB + r] = rhs[I * TB + r] - acc;
     }
     __syncthreads();
-    // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I, one
-    // wavefront per tile pair, lane 8r + c computing element (r, c) (the
-    // rows of L_IJ and L_KJ it reads are each shared by eight lanes).
-    // Look-ahead: wave 0 updates only tile (J+1, J+1) and then factors it,
-    // while the other wavefronts update the rest, so the serial diagonal
-    // factorization overlaps the trailing update.
+    // (3) trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I on the fp64
+    // matrix cores.  The trailing tiles are taken in 2 x 2 blocks of 16 x 16
+    // (block rows and columns of two tile rows each, the last one ragged when
+    // the count is odd); one wavefront per block computes
+    // D = C + (-L_I) L_K^T with two 16x16x4 fp64 MFMAs (the panel's eight
+    // columns, four per MFMA) and stores the tiles on or below the diagonal.
+    // Lane layout of the MFMA: A row l % 16, k l / 16; B column l % 16, k
+    // l / 16; D row l / 16 + 4 v, column l % 16 (v = 0..3).
+    // Look-ahead: wave 0 takes block (0, 0), which holds tile (J+1, J+1),
+    // and then factors that tile, while the other wavefronts update the
+    // rest, so the serial diagonal factorization overlaps the update.
     {
       const int nrem = T - J - 1;
-      const int npair = nrem * (nrem + 1) / 2;
-      const int r = (tid & 63) >> 3, c = tid & 7;
-      const int wave = tid >> 6;
-      int u = 0;  // tile row of this wave's current pair, advanced incrementally
-      for (int p = wave; p < (wave == 0 ? min(npair, 1) : npair); p += (wave == 0 ? 1 : BLOCK / 64 - 1)) {
-        while ((u + 1) * (u + 2) / 2 <= p) ++u;
-        const int v = p - u * (u + 1) / 2;
-        const int I = J + 1 + u, K = J + 1 + v;
-        // 32-bit tile offsets (k <= 4096 keeps them below 2^24)
-        const double *LI = STAGE ? P + (u + 1) * (TB * TB) : M + (I * (I + 1) / 2 + J) * (TB * TB);
-        const double *LK = STAGE ? P + (v + 1) * (TB * TB) : M + (K * (K + 1) / 2 + J) * (TB * TB);
-        double *C = M + (I * (I + 1) / 2 + K) * (TB * TB) + sw(r, c);
-        // every load issued before the first product uses one
-        double li[TB], lk[TB];
+      const int nb = (nrem + 1) >> 1;
+      const int nblk = nb * (nb + 1) / 2;
+      const int lane = tid & 63, wave = tid >> 6;
+      const int li = lane & 15, lk = lane >> 4;
+      int u = 0;  // block row of this wave's current block, advanced incrementally
+      for (int q = wave; q < (wave == 0 ? min(nblk, 1) : nblk); q += (wave == 0 ? 1 : BLOCK / 64 - 1)) {
+        while ((u + 1) * (u + 2) / 2 <= q) ++u;
+        const int v = q - u * (u + 1) / 2;
+        const int I0 = J + 1 + 2 * u, K0 = J + 1 + 2 * v;
+        // operands: row li of the 16 x 8 panels of block row u and block column v
+        const int Ia = I0 + (li >> 3), Kb = K0 + (li >> 3), ra = li & 7;
+        const double *LA = STAGE ? P + (Ia - J) * (TB * TB) : M + (Ia * (Ia + 1) / 2 + J) * (TB * TB);
+        const double *LB = STAGE ? P + (Kb - J) * (TB * TB) : M + (Kb * (Kb + 1) / 2 + J) * (TB * TB);
+        const double a0 = Ia < T ? -LA[sw(ra, lk)] : 0.0, a1 = Ia < T ? -LA[sw(ra, lk + 4)] : 0.0;
+        const double b0 = Kb < T ? LB[sw(ra, lk)] : 0.0, b1 = Kb < T ? LB[sw(ra, lk + 4)] : 0.0;
+        // accumulator: rows lk + 4 v, column li of the block
+        const int Kc = K0 + (li >> 3), cc = li & 7;
+        mfma_d4 acc;
 #pragma unroll
-        for (int m = 0; m < TB; ++m) li[m] = LI[sw(r, m)];
+        for (int w = 0; w < 4; ++w) {
+          const int i = lk + 4 * w, Ic = I0 + (i >> 3);
+          acc[w] = (Ic < T && Kc <= Ic) ? M[(Ic * (Ic + 1) / 2 + Kc) * (TB * TB) + sw(i & 7, cc)] : 0.0;
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
 #pragma unroll
-        for (int m = 0; m < TB; ++m) lk[m] = LK[sw(c, m)];
-        const double c0 = *C;
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < TB; ++m) s = s + li[m] * lk[m];
-        *C = c0 - s;
+        for (int w = 0; w < 4; ++w) {
+          const int i = lk + 4 * w, Ic = I0 + (i >> 3);
+          if (Ic < T && Kc <= Ic) M[(Ic * (Ic + 1) / 2 + Kc) * (TB * TB) + sw(i & 7, cc)] = acc[w];
+        }
       }
       if (wave == 0 && J + 1 < T) {
         __threadfence_block();  // this wavefront's update of tile (J+1, J+1) is read by other lanes
