@@ -643,7 +643,10 @@ __device__ bool tiled_solve(double *M, int k, const double *nx, const double *ny
     for (int c = 0; c < TB; ++c) {
       const double piv = read_lane(row[c], c);
       bad = bad || !(piv > thr_u);
-      const double l = sqrt(fmax(piv, 0.0)), inv = 1.0 / l;
+      // one reciprocal square root on the serial chain instead of a square
+      // root and a division (both within an ulp or so; a failed pivot is
+      // redone by the pivoted path anyway)
+      const double pv = fmax(piv, 0.0), inv = rsqrt(pv), l = pv * inv;
       if (r > c) row[c] = row[c] * inv;
       if (r == c) row[c] = l;
 #pragma unroll
