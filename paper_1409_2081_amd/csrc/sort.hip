@@ -18,6 +18,8 @@ constexpr int kSmallSort = 4096;
 constexpr int kRadixBlock = 256;
 constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kRadixBlock * kRadixItems;  // keys per block
+constexpr int kScanInScatter = 64;  // up to this many tiles the scatter scans the counts itself
+static_assert(kRadixBlock == 256, "one thread per digit in the scatter's bucket bases");
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
@@ -120,6 +122,11 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(const uint64_t *keys
   hist[(int64_t)tid * nblocks + blockIdx.x] = h[tid];
 }
 
+// SCAN: hist holds the raw (digit, tile) counts and every workgroup derives
+// its 256 bucket bases from them (all tiles' counts of each digit, and those
+// of the tiles before its own): the separate scan launch is saved where the
+// count table is small.  Otherwise hist holds the exclusive scan already.
+template <bool SCAN>
 __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint64_t *kin, const uint32_t *vin,
                                                                uint64_t *kout, uint32_t *vout, int64_t n,
                                                                int shift, const uint32_t *hist,
@@ -129,7 +136,29 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint64_t *k
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  base[tid] = hist[(int64_t)tid * nblocks + blockIdx.x];
+  if (SCAN) {
+    // digit tid: its count over all tiles and over the tiles before this one
+    uint32_t tot = 0, pre = 0;
+    for (int b = 0; b < nblocks; ++b) {
+      const uint32_t h = hist[(int64_t)tid * nblocks + b];
+      tot += h;
+      pre += b < (int)blockIdx.x ? h : 0u;
+    }
+    // exclusive scan of the totals over the 256 digits (Hillis-Steele in LDS)
+    base[tid] = tot;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t v = tid >= off ? base[tid - off] : 0u;
+      __syncthreads();
+      base[tid] += v;
+      __syncthreads();
+    }
+    const uint32_t excl = base[tid] - tot;
+    __syncthreads();
+    base[tid] = excl + pre;
+  } else {
+    base[tid] = hist[(int64_t)tid * nblocks + blockIdx.x];
+  }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   const int64_t tile = (int64_t)blockIdx.x * kRadixTile;
   for (int it = 0; it < kRadixItems; ++it) {
@@ -191,8 +220,12 @@ void sort_pairs(SortBufs &b, int64_t n, int key_bits, hipStream_t s, bool &in_al
   const int hi_bit = key_bits < 0 ? -key_bits : key_bits;
   for (int shift = lo_bit; shift < hi_bit; shift += 8) {
     k_radix_hist<<<nblocks, kRadixBlock, 0, s>>>(kin, n, shift, b.hist, nblocks);
-    k_scan_single<<<1, 1024, 0, s>>>(b.hist, (int64_t)nblocks * 256, nullptr);
-    k_radix_scatter<<<nblocks, kRadixBlock, 0, s>>>(kin, vin, kout, vout, n, shift, b.hist, nblocks);
+    if (nblocks <= kScanInScatter) {
+      k_radix_scatter<true><<<nblocks, kRadixBlock, 0, s>>>(kin, vin, kout, vout, n, shift, b.hist, nblocks);
+    } else {
+      k_scan_single<<<1, 1024, 0, s>>>(b.hist, (int64_t)nblocks * 256, nullptr);
+      k_radix_scatter<false><<<nblocks, kRadixBlock, 0, s>>>(kin, vin, kout, vout, n, shift, b.hist, nblocks);
+    }
     uint64_t *tk = kin; kin = kout; kout = tk;
     uint32_t *tv = vin; vin = vout; vout = tv;
     in_alt = !in_alt;
